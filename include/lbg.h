@@ -1,0 +1,152 @@
+/*
+ * lbg -- level-synchronous BFS and SSSP with load-balanced frontier expansion
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Dynamic Load Balancing Strategies for Graph Applications on GPUs"
+ * (Raval, Nasre, Kumar, R, Vadhiyar, Pingali; arXiv 1711.00231).
+ *   - BFS: each level expands the current frontier along out-edges; a newly
+ *     discovered node gets level+1 (Section IV; the distributivity remark of
+ *     Section II-B makes the per-edge form legal).
+ *   - SSSP: data-driven Bellman-Ford: every frontier node u relaxes its
+ *     out-arcs, dist[v] = min(dist[v], dist[u] + w(u,v)) with an atomic
+ *     minimum, and every improved v joins the next worklist; the loop ends
+ *     when the worklist is empty (Algorithm "SSSP Pseudocode illustrating
+ *     Edge-Based Parallelism", Section II-B, and its workload-decomposition
+ *     variant, Section III-A).
+ * Work assignment strategies (Section II and III-A):
+ *   LBG_NODE      one thread per frontier node (the node-based baseline, BS)
+ *   LBG_EDGE      one thread per worklist edge over a COO source array (the
+ *                 edge-based baseline, EP, with work-chunked pushes)
+ *   LBG_BALANCED  workload decomposition: the frontier's edges are cut into
+ *                 equal contiguous tiles that ignore node boundaries, so hubs
+ *                 are shared by many workgroups (WD)
+ *   LBG_AUTO      currently LBG_BALANCED
+ *
+ * Conventions for every entry point
+ *   - Graph in CSR (Section I): offsets[n+1] int32 (offsets[0] = 0,
+ *     non-decreasing, offsets[n] = m), cols[m] int32 in [0, n), weights[m]
+ *     uint32.  Duplicate arcs and self-loops are allowed.
+ *   - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
+ *     tensors), except `stats` (host).  The caller owns every buffer; the
+ *     library allocates no device memory and keeps no state between calls
+ *     other than process-wide profiling counters and one small pinned host
+ *     word per thread.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *     work is ordered on it.  The call returns after the solve has finished
+ *     on the stream (the level loop reads the frontier size back to decide
+ *     when to stop), so outputs are ready when it returns LBG_OK.
+ *   - Argument errors are detected on the host before any launch; the call
+ *     then returns a negative lbg_status, outputs are untouched and
+ *     lbg_last_error() describes the problem.  A full structural check of the
+ *     CSR is O(n + m) and therefore opt-in: lbg_validate_csr().
+ *   - Thread safety: concurrent calls are safe on distinct workspaces.
+ */
+#ifndef LBG_H
+#define LBG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBG_OK = 0,
+  LBG_EINVAL = -1,     /* bad argument (null pointer, n <= 0, bad strategy) */
+  LBG_ERANGE = -2,     /* src out of [0, n), m > INT32_MAX, m < 0 */
+  LBG_ENOMEM = -3,     /* workspace smaller than lbg_workspace_bytes() */
+  LBG_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
+  LBG_EOVERFLOW = -5,  /* device-side capacity guard tripped (library bug) */
+  LBG_EINTERNAL = -6   /* level count exceeded n + 1 (library bug or bad CSR) */
+} lbg_status;
+
+typedef enum {
+  LBG_AUTO = 0,
+  LBG_NODE = 1,
+  LBG_EDGE = 2,
+  LBG_BALANCED = 3
+} lbg_strategy;
+
+/* Counters of one solve (host struct, filled when `stats` is not NULL).
+ * levels: number of non-empty frontiers (BFS: eccentricity of src + 1;
+ *         SSSP: Bellman-Ford iterations).
+ * frontier_entries: total worklist entries processed (nodes; LBG_EDGE: edges).
+ * edges_scanned: total arcs relaxed (BFS: the arcs leaving reached nodes;
+ *         SSSP: at least that, re-relaxations included).
+ * updates: successful distance improvements (SSSP) or discoveries (BFS). */
+typedef struct {
+  int32_t levels;
+  int32_t reserved;
+  int64_t frontier_entries;
+  int64_t edges_scanned;
+  int64_t updates;
+} lbg_stats;
+
+/* Bytes of device workspace a bfs (is_sssp = 0) or sssp (is_sssp = 1) call
+ * with this strategy needs for a graph of n nodes and m arcs.  Returns 0 for
+ * invalid arguments.  Node-based and balanced strategies need O(n + m/tile)
+ * (CSR only, the space argument of Section III-A); the edge-based one needs
+ * two edge worklists of m entries (the COO cost of Section II-B). */
+size_t lbg_workspace_bytes(int32_t n, int64_t m, int32_t strategy, int32_t is_sssp);
+
+/* BFS levels from src.  levels_out[v] = hop distance of v from src along
+ * out-arcs, INT32_MAX if v is unreachable.  workspace: device buffer of at
+ * least lbg_workspace_bytes(n, m, strategy, 0) bytes, 256-byte aligned, that
+ * the call overwrites.  coo_src: device int32[m], the source node of every
+ * arc in CSR order; required for LBG_EDGE, ignored otherwise (may be NULL). */
+int lbg_bfs(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, int32_t src,
+            int32_t* levels_out, void* workspace, size_t workspace_bytes, int32_t strategy,
+            const int32_t* coo_src, lbg_stats* stats, void* stream);
+
+/* SSSP distances from src.  dist_out[v] = minimum total weight of a directed
+ * path from src to v, UINT32_MAX if unreachable.  Precondition: every finite
+ * shortest-path weight is below UINT32_MAX (e.g. (n-1) * max weight <
+ * UINT32_MAX); distances are exact integers, so the result is bit-identical
+ * whatever the order in which relaxations happen.  Other arguments as for
+ * lbg_bfs, with lbg_workspace_bytes(n, m, strategy, 1). */
+int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+             int64_t m, int32_t src, uint32_t* dist_out, void* workspace, size_t workspace_bytes,
+             int32_t strategy, const int32_t* coo_src, lbg_stats* stats, void* stream);
+
+/* Structural check of a CSR graph on the device: offsets[0] == 0,
+ * non-decreasing offsets, offsets[n] == m, every col in [0, n).  Needs
+ * lbg_workspace_bytes(n, m, LBG_NODE, 0) bytes of workspace.  Returns LBG_OK
+ * or LBG_EINVAL (with a message naming the first kind of defect found). */
+int lbg_validate_csr(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Human-readable message for the last non-OK return on the calling thread. */
+const char* lbg_last_error(void);
+
+/* Per-kernel timing of the frontier-expansion kernels, for roofline
+ * reporting.  While enabled, every expansion launch is bracketed by HIP events
+ * on the caller's stream and its duration is accumulated process-wide,
+ * together with the work it did, separately for BFS and SSSP solves (they run
+ * different kernels).  enable = 0 stops collection; reset = 1 clears the
+ * totals. */
+void lbg_profile_enable(int32_t enable, int32_t reset);
+
+typedef struct {
+  int64_t launches;          /* expansion kernel launches that had work */
+  int64_t empty_launches;    /* launches that found an empty frontier */
+  double kernel_ms;          /* summed duration of the launches with work */
+  double empty_ms;           /* summed duration of the empty launches */
+  int64_t frontier_entries;  /* worklist entries they consumed */
+  int64_t edges_scanned;     /* arcs they relaxed */
+  int64_t updates;           /* successful distance improvements/discoveries */
+} lbg_profile;
+
+/* Totals of BFS (is_sssp = 0) or SSSP (is_sssp = 1) solves since the last reset. */
+void lbg_profile_read(int32_t is_sssp, lbg_profile* out);
+
+/* Tile of edges one workgroup of the balanced expansion processes (the
+ * granularity of the workload decomposition), and the persistent grid size
+ * used on the current device.  For reporting and tests. */
+int32_t lbg_tile_edges(void);
+int32_t lbg_grid_blocks(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

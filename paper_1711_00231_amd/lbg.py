@@ -1,0 +1,233 @@
+"""Thin Python binding of the lbg C ABI (include/lbg.h).
+
+Argument marshalling only: every step of BFS/SSSP runs in the HIP kernels of
+liblbg.so.  torch provides device memory and the current HIP stream.  If the
+library is not built, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbg.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+AUTO, NODE, EDGE, BALANCED = 0, 1, 2, 3
+STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED}
+BFS_INF = 2**31 - 1
+SSSP_INF = 2**32 - 1
+
+
+class LbgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbg error {code}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("frontier_entries", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
+                ("updates", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("empty_launches", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double), ("empty_ms", ctypes.c_double),
+                ("frontier_entries", ctypes.c_int64),
+                ("edges_scanned", ctypes.c_int64), ("updates", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.lbg_workspace_bytes.restype = sz
+    lib.lbg_workspace_bytes.argtypes = [i32, i64, i32, i32]
+    lib.lbg_bfs.restype = ctypes.c_int
+    lib.lbg_bfs.argtypes = [vp, vp, i32, i64, i32, vp, vp, sz, i32, vp, ctypes.POINTER(Stats), vp]
+    lib.lbg_sssp.restype = ctypes.c_int
+    lib.lbg_sssp.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, sz, i32, vp,
+                             ctypes.POINTER(Stats), vp]
+    lib.lbg_validate_csr.restype = ctypes.c_int
+    lib.lbg_validate_csr.argtypes = [vp, vp, i32, i64, vp, sz, vp]
+    lib.lbg_last_error.restype = ctypes.c_char_p
+    lib.lbg_last_error.argtypes = []
+    lib.lbg_profile_enable.restype = None
+    lib.lbg_profile_enable.argtypes = [i32, i32]
+    lib.lbg_profile_read.restype = None
+    lib.lbg_profile_read.argtypes = [i32, ctypes.POINTER(Profile)]
+    lib.lbg_tile_edges.restype = i32
+    lib.lbg_tile_edges.argtypes = []
+    lib.lbg_grid_blocks.restype = i32
+    lib.lbg_grid_blocks.argtypes = []
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise LbgError(rc, lib.lbg_last_error().decode())
+
+
+def _strategy(s) -> int:
+    if isinstance(s, str):
+        return STRATEGIES[s]
+    return int(s)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_bytes(n: int, m: int, strategy="balanced", sssp: bool = False) -> int:
+    return int(lib.lbg_workspace_bytes(n, m, _strategy(strategy), int(sssp)))
+
+
+@dataclass
+class DeviceGraph:
+    """A CSR graph resident in device memory (int32 offsets/cols, uint32
+    weights stored in an int32 tensor).  ``coo_src`` is built only on demand
+    (the edge-based strategy needs it)."""
+
+    offsets: torch.Tensor
+    cols: torch.Tensor
+    weights: torch.Tensor | None
+    coo_src: torch.Tensor | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets.numel() - 1)
+
+    @property
+    def m(self) -> int:
+        return int(self.cols.numel())
+
+    @classmethod
+    def from_numpy(cls, offsets, cols, weights=None, device="cuda", with_coo=False):
+        import numpy as np
+
+        off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int32)).to(device)
+        c = torch.from_numpy(np.ascontiguousarray(cols, dtype=np.int32)).to(device)
+        w = None
+        if weights is not None:
+            w = torch.from_numpy(np.ascontiguousarray(weights, dtype=np.uint32).view(np.int32)).to(device)
+        g = cls(off, c, w)
+        if with_coo:
+            g.ensure_coo()
+        return g
+
+    def ensure_coo(self) -> torch.Tensor:
+        if self.coo_src is None:
+            deg = (self.offsets[1:] - self.offsets[:-1]).to(torch.int64)
+            self.coo_src = torch.repeat_interleave(
+                torch.arange(self.n, dtype=torch.int32, device=self.offsets.device), deg)
+            if self.coo_src.numel() == 0:
+                self.coo_src = torch.zeros(1, dtype=torch.int32, device=self.offsets.device)
+        return self.coo_src
+
+
+class Workspace:
+    """Caller-owned device workspace, grown on demand and reused."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def _ws(workspace, nbytes, device):
+    if workspace is None:
+        key = str(device)
+        workspace = _default_ws.setdefault(key, Workspace(device))
+    return workspace.get(nbytes)
+
+
+def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None = None,
+        workspace: Workspace | None = None, stats: bool = False, stream=None):
+    """Levels from ``src`` (int32, INT32_MAX = unreachable).  Returns the
+    tensor, or (tensor, stats dict) if ``stats``."""
+    s = _strategy(strategy)
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    need = workspace_bytes(g.n, g.m, s, False)
+    ws = _ws(workspace, need, g.offsets.device)
+    coo = g.ensure_coo() if s == EDGE else None
+    st = Stats()
+    rc = lib.lbg_bfs(_ptr(g.offsets), _ptr(g.cols), g.n, g.m, int(src), _ptr(out), _ptr(ws),
+                     ws.numel(), s, _ptr(coo), ctypes.byref(st) if stats else None, _stream(stream))
+    _check(rc)
+    return (out, st.as_dict()) if stats else out
+
+
+def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None = None,
+         workspace: Workspace | None = None, stats: bool = False, stream=None):
+    """Distances from ``src`` as an int32 tensor holding uint32 bit patterns
+    (use ``.view(torch.uint32)``; UINT32_MAX = unreachable)."""
+    s = _strategy(strategy)
+    if g.weights is None:
+        raise ValueError("sssp needs weights")
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    need = workspace_bytes(g.n, g.m, s, True)
+    ws = _ws(workspace, need, g.offsets.device)
+    coo = g.ensure_coo() if s == EDGE else None
+    st = Stats()
+    rc = lib.lbg_sssp(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(src),
+                      _ptr(out), _ptr(ws), ws.numel(), s, _ptr(coo),
+                      ctypes.byref(st) if stats else None, _stream(stream))
+    _check(rc)
+    return (out, st.as_dict()) if stats else out
+
+
+def validate_csr(g: DeviceGraph, workspace: Workspace | None = None, stream=None) -> None:
+    need = workspace_bytes(g.n, g.m, NODE, False)
+    ws = _ws(workspace, need, g.offsets.device)
+    _check(lib.lbg_validate_csr(_ptr(g.offsets), _ptr(g.cols), g.n, g.m, _ptr(ws), ws.numel(),
+                                _stream(stream)))
+
+
+def profile_enable(enable: bool = True, reset: bool = True) -> None:
+    lib.lbg_profile_enable(int(enable), int(reset))
+
+
+def profile_read(sssp: bool) -> dict:
+    """Expansion-kernel totals of BFS (sssp=False) or SSSP solves since the
+    last reset."""
+    p = Profile()
+    lib.lbg_profile_read(int(sssp), ctypes.byref(p))
+    return p.as_dict()
+
+
+def tile_edges() -> int:
+    return int(lib.lbg_tile_edges())
+
+
+def grid_blocks() -> int:
+    return int(lib.lbg_grid_blocks())

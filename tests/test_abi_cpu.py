@@ -1,0 +1,104 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes workspaces by the documented formulas and rejects bad
+arguments on the host before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbg.h")
+
+lbgmod = pytest.importorskip("paper_1711_00231_amd.lbg",
+                             reason="liblbg.so not built (run __graft_entry__.build())")
+lib = lbgmod.lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbg_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "lbg_bfs" in names and "lbg_sssp" in names
+    raw = ctypes.CDLL(lbgmod.LIB_PATH)
+    missing = [f for f in names if not hasattr(raw, f)]
+    assert not missing, missing
+
+
+def test_workspace_formulas():
+    T = lbgmod.tile_edges()
+    assert T > 0 and T % 256 == 0
+    al = lambda x: (x + 255) // 256 * 256
+    n, m = 1000, 123457
+    ctl = 256
+    # BFS, node-based / balanced: visited bitmap + 2 x (3 node arrays + tile marks)
+    tiles = (m + T - 1) // T + 2
+    exp_bfs = ctl + al(4 * ((n + 31) // 32)) + 2 * (3 * al(4 * n) + al(4 * tiles))
+    assert lbgmod.workspace_bytes(n, m, "balanced", False) == exp_bfs
+    assert lbgmod.workspace_bytes(n, m, "node", False) == exp_bfs
+    assert lbgmod.workspace_bytes(n, m, "auto", False) == exp_bfs
+    exp_sssp = ctl + al(4 * n) + 2 * (3 * al(4 * n) + al(4 * tiles))
+    assert lbgmod.workspace_bytes(n, m, "balanced", True) == exp_sssp
+    # edge-based: two worklists of m arc ids (the COO-scale cost, Section II-B)
+    assert lbgmod.workspace_bytes(n, m, "edge", False) == ctl + al(4 * ((n + 31) // 32)) + 2 * al(4 * m)
+    assert lbgmod.workspace_bytes(n, m, "edge", True) == ctl + al(4 * n) + 2 * al(4 * m)
+    # CSR strategies stay O(n + m / tile); the edge one grows with m
+    assert lbgmod.workspace_bytes(n, 50 * m, "balanced", False) < lbgmod.workspace_bytes(n, 50 * m, "edge", False) / 10
+    # invalid arguments
+    assert lbgmod.workspace_bytes(0, 10, "balanced", False) == 0
+    assert lbgmod.workspace_bytes(10, -1, "balanced", False) == 0
+    assert lbgmod.workspace_bytes(10, 2**31, "balanced", False) == 0
+    assert lib.lbg_workspace_bytes(10, 10, 99, 0) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails a host check
+WS = ctypes.c_void_p(0x10000)   # 256-byte aligned fake device address
+
+
+def _bfs(n=10, m=20, src=0, offsets=FAKE, cols=FAKE, out=FAKE, ws=WS, ws_bytes=1 << 40,
+         strategy=lbgmod.BALANCED, coo=None):
+    return lib.lbg_bfs(offsets, cols, n, m, src, out, ws, ws_bytes, strategy, coo, None, None)
+
+
+def _sssp(n=10, m=20, src=0, weights=FAKE, strategy=lbgmod.BALANCED, coo=None, ws_bytes=1 << 40):
+    return lib.lbg_sssp(FAKE, FAKE, weights, n, m, src, FAKE, WS, ws_bytes, strategy, coo, None, None)
+
+
+@pytest.mark.parametrize("kwargs, code", [
+    (dict(n=0), lbgmod.EINVAL),
+    (dict(n=-5), lbgmod.EINVAL),
+    (dict(m=-1), lbgmod.ERANGE),
+    (dict(m=2**31), lbgmod.ERANGE),
+    (dict(src=10), lbgmod.ERANGE),
+    (dict(src=-1), lbgmod.ERANGE),
+    (dict(offsets=None), lbgmod.EINVAL),
+    (dict(out=None), lbgmod.EINVAL),
+    (dict(ws=None), lbgmod.EINVAL),
+    (dict(cols=None), lbgmod.EINVAL),
+    (dict(strategy=7), lbgmod.EINVAL),
+    (dict(strategy=lbgmod.EDGE), lbgmod.EINVAL),          # no coo_src
+    (dict(ws=ctypes.c_void_p(0x10010)), lbgmod.EINVAL),  # misaligned workspace
+    (dict(ws_bytes=100), lbgmod.ENOMEM),
+])
+def test_bfs_argument_errors(kwargs, code):
+    assert _bfs(**kwargs) == code
+    assert lib.lbg_last_error().decode()
+
+
+def test_sssp_argument_errors():
+    assert _sssp(weights=None) == lbgmod.EINVAL
+    assert _sssp(strategy=lbgmod.EDGE) == lbgmod.EINVAL
+    assert _sssp(ws_bytes=16) == lbgmod.ENOMEM
+    assert _sssp(src=99) == lbgmod.ERANGE
+    assert "src" in lib.lbg_last_error().decode()
+
+
+def test_validate_csr_argument_errors():
+    assert lib.lbg_validate_csr(FAKE, FAKE, 0, 5, WS, 1 << 20, None) == lbgmod.EINVAL
+    assert lib.lbg_validate_csr(FAKE, FAKE, 5, -2, WS, 1 << 20, None) == lbgmod.ERANGE
+    assert lib.lbg_validate_csr(None, FAKE, 5, 5, WS, 1 << 20, None) == lbgmod.EINVAL
+    assert lib.lbg_validate_csr(FAKE, FAKE, 5, 5, WS, 8, None) == lbgmod.ENOMEM

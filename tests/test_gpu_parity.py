@@ -1,0 +1,189 @@
+"""GPU parity: BFS levels and SSSP distances from the HIP library (called
+through the C ABI binding) against the CPU oracle, bit for bit, for every
+work-assignment strategy, on edge cases, on inputs spanning many tiles with a
+ragged tail, and at the full sizes of the workloads the benchmark times."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import pins
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+from paper_1711_00231_amd import lbg  # noqa: E402  (fails loudly if liblbg.so is missing)
+
+STRATS = ["node", "edge", "balanced"]
+O = oracle.get()
+
+
+def _dev(g):
+    return lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights)
+
+
+def _gpu_bfs(dg, s, strat, **kw):
+    out = lbg.bfs(dg, int(s), strategy=strat, **kw)
+    if isinstance(out, tuple):
+        return out[0].cpu().numpy(), out[1]
+    return out.cpu().numpy()
+
+
+def _gpu_sssp(dg, s, strat, **kw):
+    out = lbg.sssp(dg, int(s), strategy=strat, **kw)
+    if isinstance(out, tuple):
+        return out[0].cpu().numpy().view(np.uint32), out[1]
+    return out.cpu().numpy().view(np.uint32)
+
+
+def _check(g, dg, srcs, strat):
+    for s in srcs:
+        exp_l = O.bfs(g.offsets, g.cols, s)
+        got_l = _gpu_bfs(dg, s, strat)
+        assert np.array_equal(got_l, exp_l), f"{g.name} bfs src={s} strat={strat}: " \
+            f"{np.count_nonzero(got_l != exp_l)} mismatches"
+        exp_d = O.dijkstra(g.offsets, g.cols, g.weights, s)
+        got_d = _gpu_sssp(dg, s, strat)
+        assert np.array_equal(got_d, exp_d), f"{g.name} sssp src={s} strat={strat}: " \
+            f"{np.count_nonzero(got_d != exp_d)} mismatches"
+
+
+# ------------------------------------------------------------- edge cases --
+@pytest.mark.parametrize("strat", STRATS)
+def test_tiny_random_graphs(strat):
+    for g, s in pins.tiny_graphs(count=40, seed=21):
+        _check(g, _dev(g), [s], strat)
+
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_degenerate_graphs(strat):
+    cases = [
+        graphgen.from_edges(1, [], [], [], "single-node"),
+        graphgen.from_edges(5, [1, 2], [2, 3], [4, 5], "isolated-source"),  # src 0 has no arcs
+        graphgen.from_edges(3, [0, 0, 0, 1], [0, 1, 1, 1], [3, 7, 2, 0], "loops-and-dups"),
+        graphgen.from_edges(4, [0, 1, 2], [1, 2, 3], [0, 0, 0], "zero-weights"),
+        pins.path_graph(3000, np.full(2999, 7)),  # long chain: 3000 levels, many level batches
+    ]
+    for g in cases:
+        _check(g, _dev(g), [0], strat)
+
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_hub_spanning_many_tiles(strat):
+    # one node with far more arcs than a tile, a second medium hub, a tail
+    T = lbg.tile_edges()
+    rng = np.random.default_rng(5)
+    n = 20000
+    hub = rng.integers(1, n, 7 * T + 13)
+    med = rng.integers(1, n, T + 1)
+    tail_src = rng.integers(1, n, 30000)
+    tail_dst = rng.integers(0, n, 30000)
+    src = np.concatenate([np.zeros(hub.size), np.full(med.size, 1), tail_src])
+    dst = np.concatenate([hub, med, tail_dst])
+    w = rng.integers(1, 50, src.size)
+    g = graphgen.from_edges(n, src, dst, w, "hub")
+    _check(g, _dev(g), [0, 1, 17], strat)
+
+
+# ------------------------------------------------- several tiles, ragged --
+@pytest.mark.parametrize("strat", STRATS)
+def test_uniform_config(strat):
+    """n = 2^14, 8 out-arcs per node, weights U[1,100], source 0."""
+    g = graphgen.uniform(14)
+    _check(g, _dev(g), [0, 1234], strat)
+
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_rmat_small(strat):
+    g = graphgen.rmat(15)
+    srcs = graphgen.sources(g, 3, graphgen.FAMILY_RMAT)
+    _check(g, _dev(g), srcs, strat)
+
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_grid_small(strat):
+    g = graphgen.grid(96)
+    h = graphgen.grid(64, shortcut_frac=0)
+    _check(g, _dev(g), [0, 4000], strat)
+    _check(h, _dev(h), [0], strat)
+
+
+def test_repeat_runs_identical():
+    """Relaxation order differs from run to run; results must not."""
+    g = graphgen.rmat(14)
+    dg = _dev(g)
+    s = int(graphgen.sources(g, 1, graphgen.FAMILY_RMAT)[0])
+    exp = O.dijkstra(g.offsets, g.cols, g.weights, s)
+    for strat in STRATS:
+        for _ in range(5):
+            assert np.array_equal(_gpu_sssp(dg, s, strat), exp)
+
+
+def test_stats_and_validate():
+    g = graphgen.rmat(13)
+    dg = _dev(g)
+    s = int(graphgen.sources(g, 1, graphgen.FAMILY_RMAT)[0])
+    lv_exp = O.bfs(g.offsets, g.cols, s)
+    reached = lv_exp != pins.BFS_INF
+    for strat in ("node", "balanced"):
+        lv, st = _gpu_bfs(dg, s, strat, stats=True)
+        assert np.array_equal(lv, lv_exp)
+        assert st["levels"] == int(lv_exp[reached].max()) + 1
+        assert st["edges_scanned"] == g.reached_arcs(reached)
+        assert st["updates"] == int(reached.sum()) - 1
+        assert st["frontier_entries"] == int((reached & (g.degrees > 0)).sum())
+    d, st = _gpu_sssp(dg, s, "balanced", stats=True)
+    assert st["edges_scanned"] >= g.reached_arcs(reached)
+    lbg.validate_csr(dg)
+    bad = graphgen.Graph("bad", g.offsets.copy(), g.cols.copy(), g.weights.copy())
+    bad.cols[7] = g.n + 3
+    with pytest.raises(lbg.LbgError, match="outside"):
+        lbg.validate_csr(_dev(bad))
+    bad2 = graphgen.Graph("bad2", g.offsets.copy(), g.cols.copy(), g.weights.copy())
+    bad2.offsets[5] = bad2.offsets[6] + 1
+    with pytest.raises(lbg.LbgError, match="decrease"):
+        lbg.validate_csr(_dev(bad2))
+
+
+def test_device_argument_errors_leave_output_untouched():
+    g = graphgen.uniform(8)
+    dg = _dev(g)
+    out = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+    with pytest.raises(lbg.LbgError):
+        lbg.bfs(dg, g.n + 1, out=out)
+    assert int((out == -7).sum()) == g.n
+
+
+# -------------------------------------------------------------- full size --
+@pytest.fixture(scope="module")
+def rmat22():
+    g = graphgen.rmat(22)
+    return g, _dev(g), graphgen.sources(g, 64, graphgen.FAMILY_RMAT)
+
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_rmat22_full(rmat22, strat):
+    """RMAT scale 22, edge factor 16 (the benchmark workload): full vectors
+    against the oracle for two of the 64 sources, certificate for a third."""
+    g, dg, srcs = rmat22
+    _check(g, dg, srcs[:2] if strat == "balanced" else srcs[:1], strat)
+    if strat == "balanced":
+        s = int(srcs[2])
+        d = _gpu_sssp(dg, s, strat)
+        assert O.certificate(g.offsets, g.cols, g.weights, s, d)[0] == 0
+        lv = _gpu_bfs(dg, s, strat)
+        assert O.certificate(g.offsets, g.cols, None, s, lv)[0] == 0
+
+
+def test_grid2048_full():
+    """2048x2048 road-like grid (and its no-shortcut companion with ~4000
+    levels): full vectors against the oracle."""
+    g = graphgen.grid(2048)
+    srcs = graphgen.sources(g, 2, graphgen.FAMILY_GRID)
+    _check(g, _dev(g), srcs[:1], "balanced")
+    h = graphgen.grid(2048, shortcut_frac=0)
+    dh = _dev(h)
+    s = int(srcs[1])
+    assert np.array_equal(_gpu_bfs(dh, s, "balanced"), O.bfs(h.offsets, h.cols, s))
