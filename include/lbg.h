@@ -74,13 +74,15 @@ typedef enum {
  * frontier_entries: total worklist entries processed (nodes; LBG_EDGE: edges).
  * edges_scanned: total arcs relaxed (BFS: the arcs leaving reached nodes;
  *         SSSP: at least that, re-relaxations included).
- * updates: successful distance improvements (SSSP) or discoveries (BFS). */
+ * updates: successful distance improvements (SSSP) or discoveries (BFS).
+ * atomics: device-scope atomics issued on node state (claims / atomicMin). */
 typedef struct {
   int32_t levels;
   int32_t reserved;
   int64_t frontier_entries;
   int64_t edges_scanned;
   int64_t updates;
+  int64_t atomics;
 } lbg_stats;
 
 /* Bytes of device workspace a bfs (is_sssp = 0) or sssp (is_sssp = 1) call
@@ -135,6 +137,7 @@ typedef struct {
   int64_t frontier_entries;  /* worklist entries they consumed */
   int64_t edges_scanned;     /* arcs they relaxed */
   int64_t updates;           /* successful distance improvements/discoveries */
+  int64_t atomics;           /* device-scope atomics issued on node state */
 } lbg_profile;
 
 /* Totals of BFS (is_sssp = 0) or SSSP (is_sssp = 1) solves since the last reset. */

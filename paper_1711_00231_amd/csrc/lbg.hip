@@ -43,7 +43,7 @@ int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
 // Workspace layout.  All offsets 256-byte aligned.
 struct Layout {
-  size_t ctl, visited, stamp, node[2], eprefix[2], estart[2], tile[2], total;
+  size_t ctl, visited, seen[2], xfilter, dstate, node[2], eprefix[2], estart[2], tile[2], total;
   uint32_t node_cap, tile_cap, edge_cap;
 };
 
@@ -57,14 +57,21 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
     return at;
   };
   L.ctl = take(sizeof(Ctl));
-  if (is_sssp) L.stamp = take(sizeof(uint32_t) * static_cast<size_t>(n));
-  else L.visited = take(sizeof(uint32_t) * ((static_cast<size_t>(n) + 31) / 32));
+  const size_t words = (static_cast<size_t>(n) + 31) / 32;
+  if (is_sssp) {
+    L.dstate = take(sizeof(unsigned long long) * static_cast<size_t>(n));
+  } else {
+    L.visited = take(sizeof(uint32_t) * words);
+    L.seen[0] = take(sizeof(uint32_t) * words);
+    L.seen[1] = take(sizeof(uint32_t) * words);
+    L.xfilter = take(sizeof(uint32_t) * words * lbg::kXcds);
+  }
   if (s == LBG_EDGE) {
     L.edge_cap = static_cast<uint32_t>(m);
     for (int b = 0; b < 2; ++b) L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(m > 0 ? m : 1));
   } else {
     L.node_cap = static_cast<uint32_t>(n);
-    L.tile_cap = static_cast<uint32_t>((m + lbg::kTile - 1) / lbg::kTile + 2);
+    L.tile_cap = static_cast<uint32_t>((m + lbg::kMinTile - 1) / lbg::kMinTile + 2);
     for (int b = 0; b < 2; ++b) {
       L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(n));
       L.eprefix[b] = take(sizeof(uint32_t) * static_cast<size_t>(n));
@@ -76,11 +83,12 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
   return L;
 }
 
-// Persistent grid: a few resident workgroups per CU, enough to cover the
-// 256 CUs of the 8 XCDs several times over.  Workgroups are dealt to XCDs
-// round-robin by the dispatcher; tiles are independent, so no remapping is
-// needed for locality.
-int grid_blocks() {
+// Persistent grids: exactly as many workgroups as can be resident at once
+// (occupancy x CUs), so tiles dealt round-robin to workgroups all start
+// immediately; workgroups are dealt to the 8 XCDs round-robin by the
+// dispatcher, which the per-XCD filter and stats lines rely on for locality
+// only (never for correctness).
+int cu_count() {
   static std::mutex mu;
   static int cached[64] = {0};
   int dev = 0;
@@ -91,10 +99,46 @@ int grid_blocks() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    cached[dev] = cus * 8;
+    cached[dev] = cus;
   }
   return cached[dev];
 }
+
+template <typename K>
+int resident_grid(K kernel) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, lbg::kBlock, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 4;
+  return per_cu * cu_count();
+}
+
+struct Grids {
+  int bal[2][2], node[2], edge[2];  // bal[is_sssp][narrow]
+};
+
+const Grids& grids() {
+  static std::mutex mu;
+  static Grids g[64];
+  static bool done[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!done[dev]) {
+    g[dev].bal[0][0] = resident_grid(lbg::k_expand_balanced<false, false>);
+    g[dev].bal[0][1] = resident_grid(lbg::k_expand_balanced<false, true>);
+    g[dev].bal[1][0] = resident_grid(lbg::k_expand_balanced<true, false>);
+    g[dev].bal[1][1] = resident_grid(lbg::k_expand_balanced<true, true>);
+    g[dev].node[0] = resident_grid(lbg::k_expand_node<false>);
+    g[dev].node[1] = resident_grid(lbg::k_expand_node<true>);
+    g[dev].edge[0] = resident_grid(lbg::k_expand_edge<false>);
+    g[dev].edge[1] = resident_grid(lbg::k_expand_edge<true>);
+    done[dev] = true;
+  }
+  return g[dev];
+}
+
+int grid_blocks() { return grids().bal[0][1]; }
 
 // Host side of the profiling counters (see lbg_profile_enable).
 std::mutex g_prof_mu;
@@ -126,6 +170,12 @@ hipEvent_t event_at(size_t i) {
     g_events.push_back(e);
   }
   return g_events[i];
+}
+
+int64_t xsum(const Ctl* c, int k) {
+  int64_t t = 0;
+  for (int x = 0; x < lbg::kXcds; ++x) t += static_cast<int64_t>(c->xstat[x][k]);
+  return t;
 }
 
 struct Problem {
@@ -178,10 +228,13 @@ int solve(const Problem& P) {
   a.coo_src = P.coo_src;
   if (P.is_sssp) {
     a.dist = static_cast<uint32_t*>(P.out);
-    a.stamp = reinterpret_cast<uint32_t*>(ws + Lay.stamp);
+    a.dstate = reinterpret_cast<unsigned long long*>(ws + Lay.dstate);
   } else {
     a.levels = static_cast<int32_t*>(P.out);
     a.visited = reinterpret_cast<uint32_t*>(ws + Lay.visited);
+    a.seen[0] = reinterpret_cast<uint32_t*>(ws + Lay.seen[0]);
+    a.seen[1] = reinterpret_cast<uint32_t*>(ws + Lay.seen[1]);
+    a.xfilter = reinterpret_cast<uint32_t*>(ws + Lay.xfilter);
   }
   for (int b = 0; b < 2; ++b) {
     a.fr[b].node = reinterpret_cast<int32_t*>(ws + Lay.node[b]);
@@ -194,6 +247,7 @@ int solve(const Problem& P) {
   a.ctl = reinterpret_cast<Ctl*>(ws + Lay.ctl);
   a.n = static_cast<uint32_t>(P.n);
   a.m = static_cast<uint32_t>(P.m);
+  a.words = static_cast<uint32_t>((static_cast<size_t>(P.n) + 31) / 32);
   a.node_cap = Lay.node_cap;
   a.tile_cap = Lay.tile_cap;
   a.edge_cap = Lay.edge_cap;
@@ -202,13 +256,17 @@ int solve(const Problem& P) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     profiling = g_prof_on;
   }
-  a.count_updates = (P.stats || profiling) ? 1u : 0u;
+  a.count_stats = (P.stats || profiling) ? 1u : 0u;
 
   Ctl* host = pinned_ctl();
   if (!host) return fail(LBG_EHIP, "hipHostMalloc of the readback word failed");
 
   const hipStream_t st = P.stream;
-  const int G = grid_blocks();
+  const Grids& GR = grids();
+  const int sv = P.is_sssp ? 1 : 0;
+  // 32-bit element offsets are enough when every array stays below 4 GiB
+  const bool narrow = P.n < (1 << 29) && P.m < (int64_t{1} << 30);
+  const int nw = narrow ? 1 : 0;
   const int init_blocks = static_cast<int>(
       std::min<int64_t>(std::max<int64_t>((static_cast<int64_t>(P.n) + lbg::kBlock - 1) / lbg::kBlock, 1), 4096));
 
@@ -224,15 +282,21 @@ int solve(const Problem& P) {
   auto launch = [&](uint32_t L) {
     if (P.is_sssp) {
       switch (strat) {
-        case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<true>), dim3(G), dim3(lbg::kBlock), 0, st, a, L); break;
-        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<true>), dim3(G), dim3(lbg::kBlock), 0, st, a, L); break;
-        default: hipLaunchKernelGGL((lbg::k_expand_balanced<true>), dim3(G), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<true>), dim3(GR.node[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        default:
+          if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          else hipLaunchKernelGGL((lbg::k_expand_balanced<true, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          break;
       }
     } else {
       switch (strat) {
-        case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<false>), dim3(G), dim3(lbg::kBlock), 0, st, a, L); break;
-        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<false>), dim3(G), dim3(lbg::kBlock), 0, st, a, L); break;
-        default: hipLaunchKernelGGL((lbg::k_expand_balanced<false>), dim3(G), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<false>), dim3(GR.node[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<false>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        default:
+          if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<false, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          else hipLaunchKernelGGL((lbg::k_expand_balanced<false, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          break;
       }
     }
   };
@@ -257,6 +321,10 @@ int solve(const Problem& P) {
         if (!e) return fail(LBG_EHIP, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e, st));
       }
+    }
+    if (P.is_sssp) {
+      hipLaunchKernelGGL(lbg::k_sssp_finish, dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, L);
+      HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -284,14 +352,16 @@ int solve(const Problem& P) {
     }
     gp.frontier_entries += static_cast<int64_t>(host->frontier_entries);
     gp.edges_scanned += static_cast<int64_t>(host->edges_scanned);
-    gp.updates += static_cast<int64_t>(host->updates);
+    gp.updates += xsum(host, 0);
+    gp.atomics += xsum(host, 1);
   }
   if (P.stats) {
     P.stats->levels = static_cast<int32_t>(host->levels);
     P.stats->reserved = 0;
     P.stats->frontier_entries = static_cast<int64_t>(host->frontier_entries);
     P.stats->edges_scanned = static_cast<int64_t>(host->edges_scanned);
-    P.stats->updates = static_cast<int64_t>(host->updates);
+    P.stats->updates = xsum(host, 0);
+    P.stats->atomics = xsum(host, 1);
   }
   return LBG_OK;
 }
@@ -366,7 +436,7 @@ void lbg_profile_read(int32_t is_sssp, lbg_profile* out) {
   *out = g_prof[is_sssp ? 1 : 0];
 }
 
-int32_t lbg_tile_edges(void) { return lbg::kTile; }
+int32_t lbg_tile_edges(void) { return static_cast<int32_t>(lbg::kMinTile); }
 
 int32_t lbg_grid_blocks(void) { return grid_blocks(); }
 

@@ -11,31 +11,48 @@ namespace lbg {
 
 constexpr int kBlock = 256;              // threads per workgroup (4 waves)
 constexpr int kWaves = kBlock / 64;
-constexpr int kItems = 4;                // edges per thread per tile (balanced)
-constexpr int kTile = kBlock * kItems;   // edges per tile
-constexpr int kQueue = 256;              // per-wave LDS push-queue entries
+constexpr int kQueue = 256;              // per-wave LDS push-queue entries (node/edge kernels)
+constexpr int kWQ = 256;                 // per-wave LDS push-queue entries (balanced kernel)
+
+// Balanced kernel: a tile is the run of consecutive edges one wavefront
+// expands at a time, 64 lanes x kItems edges.  BFS carries 16 items per lane,
+// SSSP (more state per arc) 8.
+template <bool kSssp>
+struct TileCfg {
+  static constexpr int kItems = kSssp ? 8 : 16;
+  static constexpr uint32_t kEdges = 64u * kItems;
+};
+constexpr uint32_t kMinTile = TileCfg<true>::kEdges;  // sizes the tile-mark arrays
+constexpr int kXcds = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
 
 // Control block at the start of the workspace.  ctr[] are the worklist tail
 // counters of three consecutive levels, packed as (nodes << 32) | edges so a
 // single 64-bit atomic reserves node slots and the matching range of the
 // next level's edge space at once (the edge prefix of Section III-A built at
 // push time, with no separate scan).
+//
+// Counters that many workgroups bump are striped per XCD (one 128-byte line
+// each): a single device-wide address serialises atomics (about 12 ns each
+// on MI355X), eight independent lines do not.
 struct Ctl {
   unsigned long long ctr[3];
-  unsigned int error;         // capacity/bounds guards, see kErr* in lbg_kernels.hpp
+  unsigned int error;         // capacity/bounds guards, kErr* below
   unsigned int levels;        // number of non-empty frontiers so far
   unsigned long long frontier_entries;
   unsigned long long edges_scanned;
-  unsigned long long updates;
   unsigned int csr_flags;     // lbg_validate_csr findings
-  unsigned int pad[5];
+  unsigned int pad0;
+  unsigned long long pad1[9];
+  unsigned long long xstat[kXcds][16];  // [x][0] updates, [x][1] global atomics issued
 };
+static_assert(sizeof(Ctl) == 128 + kXcds * 128, "Ctl layout");
 
 // One worklist (frontier) buffer.  For node worklists entry i holds the node,
 // the position of its first edge in this level's edge space (strictly
 // increasing in i because every stored node has out-degree >= 1) and the CSR
 // offset of its first arc.  tile_node[t] is the entry whose edge range holds
-// edge t * kTile: the per-tile NodeOffset of the workload decomposition.
+// edge t * T (T = the tile size of the kernel that consumes the worklist):
+// the per-tile NodeOffset of the workload decomposition.
 // Edge worklists (edge-based strategy) use `node` as the list of arc ids.
 struct Frontier {
   int32_t* node;
@@ -51,17 +68,48 @@ struct KArgs {
   const int32_t* coo_src;
   int32_t* levels;       // BFS output
   uint32_t* dist;        // SSSP output
-  uint32_t* visited;     // BFS: one bit per node
-  uint32_t* stamp;       // SSSP: last level a node was queued for
+  uint32_t* visited;     // BFS: one bit per node (authoritative, set by atomicOr only)
+  uint32_t* seen[2];     // BFS: read-only-per-level snapshots of `visited` (double-buffered)
+  uint32_t* xfilter;     // BFS: per-XCD advisory copy of `visited`, kXcds x words
+  unsigned long long* dstate;  // SSSP: (distance << 32) | iteration of last improvement
   Frontier fr[2];
   Ctl* ctl;
   uint32_t n;
   uint32_t m;
+  uint32_t words;        // (n + 31) / 32
   uint32_t node_cap;     // entries per node worklist
   uint32_t tile_cap;     // entries per tile_node array
   uint32_t edge_cap;     // entries per edge worklist
-  uint32_t count_updates;
+  uint32_t count_stats;
 };
+
+// Ctl::error bits.  None can trip for a well-formed CSR; they turn what
+// would otherwise be an out-of-bounds access into an LBG_EOVERFLOW return.
+constexpr unsigned kErrNodeCap = 1u, kErrTileCap = 2u, kErrEdgeCap = 4u, kErrBadArc = 8u,
+                   kErrBadTile = 16u;
+
+// Address of element idx of an array.  With kNarrow the byte offset is
+// formed in 32 bits, so the access is a uniform (SGPR) base plus a 32-bit
+// VGPR offset: one VGPR per address instead of two and no 64-bit address
+// arithmetic, which matters with 16 loads in flight per lane.  Valid when
+// every array the kernel touches is below 4 GiB (n < 2^29, m < 2^30); the
+// host picks the wide form otherwise.
+template <bool kNarrow, typename T>
+__device__ __forceinline__ T* at(T* base, uint32_t idx) {
+  if constexpr (kNarrow)
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) +
+                                static_cast<uint32_t>(idx * static_cast<uint32_t>(sizeof(T))));
+  else
+    return base + idx;
+}
+template <bool kNarrow, typename T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t idx) {
+  if constexpr (kNarrow)
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                      static_cast<uint32_t>(idx * static_cast<uint32_t>(sizeof(T))));
+  else
+    return base + idx;
+}
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -116,7 +164,7 @@ struct WaveQueue {
 
   // Node worklist flush: writes node / eprefix / estart and, if kMarks, the
   // tile_node marks of every tile whose first edge falls in an entry.
-  template <bool kMarks>
+  template <bool kMarks, uint32_t kTileE = kMinTile>
   __device__ __forceinline__ void flush_nodes(const KArgs& a, Frontier out, int ctr_idx) {
     if (count == 0) return;
     const uint32_t lane = lane_id();
@@ -149,15 +197,15 @@ struct WaveQueue {
           out.eprefix[i] = p;
           out.estart[i] = qs[k];
           if (kMarks) {
-            uint32_t t = (p + kTile - 1) / kTile;
+            uint32_t t = (p + kTileE - 1) / kTileE;
             const uint32_t end = p + static_cast<uint32_t>(d);
-            for (; t * static_cast<unsigned long long>(kTile) < end; ++t) {
+            for (; t * static_cast<unsigned long long>(kTileE) < end; ++t) {
               if (t < a.tile_cap) out.tile_node[t] = static_cast<int32_t>(i);
-              else atomicOr(&a.ctl->error, 2u);  // tile capacity
+              else atomicOr(&a.ctl->error, kErrTileCap);
             }
           }
         } else {
-          atomicOr(&a.ctl->error, 1u);  // node capacity
+          atomicOr(&a.ctl->error, kErrNodeCap);
         }
       }
     }
@@ -192,7 +240,7 @@ struct WaveQueue {
         if (static_cast<unsigned long long>(p) + static_cast<uint32_t>(d) <= a.edge_cap) {
           for (int32_t t = 0; t < d; ++t) out[p + t] = s + t;
         } else {
-          atomicOr(&a.ctl->error, 4u);  // edge capacity
+          atomicOr(&a.ctl->error, kErrEdgeCap);
         }
       }
     }
@@ -213,6 +261,140 @@ struct WaveQueue {
     }
     count += c;
     __builtin_amdgcn_wave_barrier();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Push path of the balanced kernel.  Each wavefront appends discovered node
+// ids to its own LDS queue (no atomic at all: the count is wave-uniform);
+// between tiles a queue that is half full is flushed by its wavefront with
+// bulk degree reads, a wave scan and ONE packed 64-bit atomic on the worklist
+// tail.  At the end of the launch the four queues of a workgroup are merged
+// into one reservation, so the tail sees about one atomic per workgroup
+// rather than one per wavefront (same-address atomics serialise at ~12 ns).
+
+// Writes worklist entry i (node v, first edge p of the level's edge space,
+// first arc s, out-degree d) and marks the tiles whose first edge it holds.
+template <bool kWithNode, uint32_t kTileE, bool kNarrow>
+__device__ __forceinline__ void write_entry(const KArgs& a, const Frontier& out, uint32_t i,
+                                            uint32_t p, int32_t v, int32_t s, int32_t d) {
+  if (i >= a.node_cap) {
+    atomicOr(&a.ctl->error, kErrNodeCap);
+    return;
+  }
+  if (kWithNode) *at<kNarrow>(out.node, i) = v;
+  *at<kNarrow>(out.eprefix, i) = p;
+  *at<kNarrow>(out.estart, i) = s;
+  const uint32_t end = p + static_cast<uint32_t>(d);
+  for (uint32_t t = (p + kTileE - 1) / kTileE; static_cast<unsigned long long>(t) * kTileE < end; ++t) {
+    if (t < a.tile_cap) *at<kNarrow>(out.tile_node, t) = static_cast<int32_t>(i);
+    else atomicOr(&a.ctl->error, kErrTileCap);
+  }
+}
+
+// Wave-direct append of the lanes with `act` set (convergent); used when a
+// wave queue cannot take a whole push.
+template <bool kWithNode, uint32_t kTileE, bool kNarrow>
+__device__ __forceinline__ void wave_append(const KArgs& a, bool act, int32_t v, const Frontier& out,
+                                            int ctr_idx) {
+  int32_t s = 0, d = 0;
+  if (act) {
+    s = *at<kNarrow>(a.offsets, v);
+    d = *at<kNarrow>(a.offsets, v + 1) - s;
+  }
+  const bool ok = act && d > 0;
+  const uint64_t mask = __ballot(ok);
+  if (mask == 0) return;
+  const uint32_t dd = ok ? static_cast<uint32_t>(d) : 0u;
+  const uint32_t inc = wave_incl_scan(dd);
+  const uint32_t tot = __shfl(inc, 63, 64);
+  unsigned long long base = 0;
+  if (lane_id() == 0)
+    base = atomicAdd(&a.ctl->ctr[ctr_idx],
+                     (static_cast<unsigned long long>(__popcll(mask)) << 32) | tot);
+  base = bcast64(base, 0);
+  if (ok)
+    write_entry<kWithNode, kTileE, kNarrow>(a, out, static_cast<uint32_t>(base >> 32) + lane_rank(mask),
+                                            static_cast<uint32_t>(base) + inc - dd, v, s, d);
+}
+
+// Queue v if `want` (convergent per wave).  `count` is wave-uniform.
+template <bool kWithNode, uint32_t kTileE, bool kNarrow>
+__device__ __forceinline__ void wq_push(const KArgs& a, int32_t* qv, uint32_t& count, bool want,
+                                        int32_t v, const Frontier& out, int ctr_idx) {
+  const uint64_t mask = __ballot(want);
+  if (mask == 0) return;
+  const uint32_t k = count + lane_rank(mask);
+  const bool fits = want && k < static_cast<uint32_t>(kWQ);
+  if (fits) qv[k] = v;
+  const uint32_t c = static_cast<uint32_t>(__popcll(mask));
+  count = min(count + c, static_cast<uint32_t>(kWQ));
+  const bool over = want && !fits;
+  if (__ballot(over)) wave_append<kWithNode, kTileE, kNarrow>(a, over, v, out, ctr_idx);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// A wave queue's flush, split so a workgroup can merge the reservations of
+// its four queues: prepare() reads degrees and scans within the wave,
+// write() stores the entries once the base of the reservation is known.
+template <bool kWithNode, uint32_t kTileE, bool kNarrow>
+struct WaveFlush {
+  static constexpr int R = kWQ / 64;
+  int32_t vs[R], ss[R], ds[R];
+  uint32_t pn[R], pe[R];
+  uint32_t tot_n, tot_e;
+
+  __device__ __forceinline__ void prepare(const KArgs& a, const int32_t* qv, uint32_t count) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t k = r * 64 + lane;
+      vs[r] = 0;
+      ss[r] = 0;
+      ds[r] = 0;
+      if (k < count) vs[r] = qv[k];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r * 64 + lane < count) {
+        ss[r] = *at<kNarrow>(a.offsets, vs[r]);
+        ds[r] = *at<kNarrow>(a.offsets, vs[r] + 1);
+      }
+    }
+    uint32_t cn = 0, ce = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ds[r] -= ss[r];
+      const uint32_t n1 = ds[r] > 0 ? 1u : 0u;
+      const uint32_t e1 = ds[r] > 0 ? static_cast<uint32_t>(ds[r]) : 0u;
+      const uint32_t in = wave_incl_scan(n1), ie = wave_incl_scan(e1);
+      pn[r] = cn + in - n1;
+      pe[r] = ce + ie - e1;
+      cn += __shfl(in, 63, 64);
+      ce += __shfl(ie, 63, 64);
+    }
+    tot_n = cn;
+    tot_e = ce;
+  }
+
+  __device__ __forceinline__ void write(const KArgs& a, const Frontier& out, uint32_t nb,
+                                        uint32_t eb) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (ds[r] > 0)
+        write_entry<kWithNode, kTileE, kNarrow>(a, out, nb + pn[r], eb + pe[r], vs[r], ss[r], ds[r]);
+  }
+
+  // Standalone flush by one wavefront.
+  __device__ __forceinline__ void flush(const KArgs& a, const int32_t* qv, uint32_t count,
+                                        const Frontier& out, int ctr_idx) {
+    prepare(a, qv, count);
+    if (tot_n == 0) return;
+    unsigned long long base = 0;
+    if (lane_id() == 0)
+      base = atomicAdd(&a.ctl->ctr[ctr_idx], (static_cast<unsigned long long>(tot_n) << 32) | tot_e);
+    base = bcast64(base, 0);
+    write(a, out, static_cast<uint32_t>(base >> 32), static_cast<uint32_t>(base));
   }
 };
 

@@ -7,14 +7,26 @@
 // from device memory, so the host can enqueue many levels without waiting;
 // a launch that finds an empty worklist returns at once.
 //
-// Relaxation (Section II-B): BFS claims an undiscovered node with an atomic
-// OR on a visited bitmap (n/8 bytes, small enough to stay in each XCD's L2)
-// and the winner writes level L+1; SSSP does alt = dist[u] + w, a plain read
-// to skip hopeless arcs, then atomicMin, and queues an improved node once
-// per iteration through an atomicExch on its stamp (the worklist condensing
-// concern of Section II-B handled at push time).  Plain reads may be stale
-// inside a launch; values only move one way (bits set, distances decrease),
-// so a stale read can only cause an extra atomic, never a missed update.
+// Relaxation (Section II-B).  Device atomics are the scarce resource on
+// MI355X (about 27 G/s chip-wide, any scope, against ~250 G/s random L2
+// reads), so each path filters with plain reads before it issues one:
+//  * BFS claims an undiscovered node with an atomic OR on a visited bitmap.
+//    An atomic on a line invalidates that line in every XCD's L2, so the hot
+//    path never reads the bitmap it claims through: it reads `seen`, a copy
+//    frozen for the level (nodes visited before level L; n/8 bytes, resident
+//    in every L2), then a per-XCD advisory copy that the XCD's own claimants
+//    update with plain stores, so an XCD issues about one atomic per new
+//    node.  The winner writes level L+1 and sets the bit in next level's
+//    `seen`, which this launch also refreshes from the current one (plain
+//    stores; a bit lost to a racing store only costs one more atomic later).
+//  * SSSP keeps (distance << 32 | iteration of last improvement) per node and
+//    relaxes with a single 64-bit atomicMin: the returned old value says both
+//    whether the arc improved the node and whether the node is already queued
+//    for this iteration (the worklist condensing concern of Section II-B is
+//    handled at push time, with no second atomic).
+// Plain reads may be stale inside a launch; values only move one way (bits
+// set, distances decrease), so a stale read can only cost an extra atomic,
+// never a missed update.
 #pragma once
 
 #include "lbg_device.hpp"
@@ -24,10 +36,6 @@ namespace lbg {
 constexpr uint32_t kBfsInf = 0x7fffffffu;
 constexpr uint32_t kSsspInf = 0xffffffffu;
 
-// Ctl::error bits.  None can trip for a well-formed CSR; they turn what
-// would otherwise be an out-of-bounds access into an LBG_EOVERFLOW return.
-constexpr unsigned kErrNodeCap = 1u, kErrTileCap = 2u, kErrEdgeCap = 4u, kErrBadArc = 8u,
-                   kErrBadTile = 16u;
 
 // Shared prologue: read this level's worklist size, clear the counter two
 // levels ahead, account the level.  Returns the packed (nodes, edges) tail.
@@ -45,17 +53,45 @@ __device__ __forceinline__ unsigned long long level_begin(const KArgs& a, uint32
   return c;
 }
 
-__device__ __forceinline__ void add_updates(const KArgs& a, uint32_t upd) {
-  if (!a.count_updates) return;
-  const uint32_t s = wave_sum(upd);
-  if (lane_id() == 0 && s) atomicAdd(&a.ctl->updates, static_cast<unsigned long long>(s));
+// Block-level reduction of the per-thread counters, then one atomic per
+// block on this XCD's stats line.  Must be reached by the whole block.
+// BFS: next level's `seen` snapshot starts as this level's (whole grid).
+__device__ __forceinline__ void refresh_seen(const KArgs& a, uint32_t L) {
+  const uint32_t* cur = a.seen[L & 1];
+  uint32_t* nxt = a.seen[(L + 1) & 1];
+  for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < a.words; k += gridDim.x * kBlock)
+    nxt[k] = cur[k];
+}
+
+__device__ __forceinline__ void add_stats(const KArgs& a, uint32_t upd, uint32_t atom) {
+  if (!a.count_stats) return;  // kernel-argument uniform
+  __shared__ uint32_t red[2][kWaves];
+  const uint32_t su = wave_sum(upd), sa = wave_sum(atom);
+  const uint32_t wid = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    red[0][wid] = su;
+    red[1][wid] = sa;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tu = 0, ta = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      tu += red[0][w];
+      ta += red[1][w];
+    }
+    const int x = blockIdx.x % kXcds;
+    if (tu) atomicAdd(&a.ctl->xstat[x][0], tu);
+    if (ta) atomicAdd(&a.ctl->xstat[x][1], ta);
+  }
 }
 
 // Relax one arc u -> v.  Returns true if v must be queued for the next
-// level; then *s / *d receive v's first arc and out-degree.
+// level; then *s / *d receive v's first arc and out-degree.  *upd counts
+// successful improvements/discoveries, *atom the global atomics issued.
 template <bool kSssp>
 __device__ __forceinline__ bool relax(const KArgs& a, uint32_t L, int32_t v, uint32_t du,
-                                      uint32_t w, uint32_t* upd, int32_t* s, int32_t* d) {
+                                      uint32_t w, uint32_t* upd, uint32_t* atom, int32_t* s,
+                                      int32_t* d) {
   if (static_cast<uint32_t>(v) >= a.n) {  // malformed cols (see lbg_validate_csr)
     atomicOr(&a.ctl->error, kErrBadArc);
     return false;
@@ -63,17 +99,26 @@ __device__ __forceinline__ bool relax(const KArgs& a, uint32_t L, int32_t v, uin
   if (!kSssp) {
     const uint32_t word = static_cast<uint32_t>(v) >> 5;
     const uint32_t bit = 1u << (v & 31);
-    if (a.visited[word] & bit) return false;
-    if (atomicOr(&a.visited[word], bit) & bit) return false;  // another lane won
+    if (a.seen[L & 1][word] & bit) return false;
+    uint32_t* f = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
+    const uint32_t fw = f[word];
+    if (fw & bit) return false;  // this XCD already claimed (or is claiming) v
+    f[word] = fw | bit;          // plain store; a lost bit only costs one more atomic
+    ++*atom;
+    if (atomicOr(&a.visited[word], bit) & bit) return false;  // another XCD won
     a.levels[v] = static_cast<int32_t>(L + 1);
+    uint32_t* sn = a.seen[(L + 1) & 1];
+    sn[word] |= bit;  // plain read-modify-write: a lost bit only costs an atomic later
     ++*upd;
   } else {
     const uint32_t alt = du + w;
-    if (alt >= a.dist[v]) return false;
-    const uint32_t old = atomicMin(&a.dist[v], alt);
-    if (alt >= old) return false;
+    if (alt >= static_cast<uint32_t>(a.dstate[v] >> 32)) return false;
+    const unsigned long long mine = (static_cast<unsigned long long>(alt) << 32) | (L + 1);
+    ++*atom;
+    const unsigned long long old = atomicMin(&a.dstate[v], mine);
+    if (alt >= static_cast<uint32_t>(old >> 32)) return false;
     ++*upd;
-    if (atomicExch(&a.stamp[v], L + 1) == L + 1) return false;  // already queued
+    if (static_cast<uint32_t>(old) == L + 1) return false;  // already queued this iteration
   }
   const int32_t s0 = a.offsets[v];
   *s = s0;
@@ -90,23 +135,32 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
   const uint32_t stride = gridDim.x * kBlock;
   for (uint32_t v = gid; v < a.n; v += stride) {
     if (kSssp) {
-      a.dist[v] = (v == static_cast<uint32_t>(src)) ? 0u : kSsspInf;
-      a.stamp[v] = 0u;
+      a.dstate[v] = (v == static_cast<uint32_t>(src)) ? 0ull
+                                                      : (static_cast<unsigned long long>(kSsspInf) << 32);
     } else {
       a.levels[v] = (v == static_cast<uint32_t>(src)) ? 0 : static_cast<int32_t>(kBfsInf);
     }
   }
   if (!kSssp) {
-    const uint32_t words = (a.n + 31) / 32;
     const uint32_t sw = static_cast<uint32_t>(src) >> 5;
-    for (uint32_t w = gid; w < words; w += stride) a.visited[w] = (w == sw) ? (1u << (src & 31)) : 0u;
+    for (uint32_t w = gid; w < a.words; w += stride) {
+      const uint32_t bits = (w == sw) ? (1u << (src & 31)) : 0u;
+      a.visited[w] = bits;
+      a.seen[0][w] = bits;
+      // seen[1] must not carry another solve's bits: level 0 may OR into a
+      // word of it before refreshing that word
+      a.seen[1][w] = 0u;
+    }
+    const uint32_t fwords = a.words * kXcds;
+    for (uint32_t w = gid; w < fwords; w += stride) a.xfilter[w] = 0u;
   }
   const int32_t s0 = a.offsets[src];
   const int32_t d0 = a.offsets[src + 1] - s0;
   if (kEdgeWl) {
     for (uint32_t k = gid; k < static_cast<uint32_t>(d0); k += stride) a.fr[0].node[k] = s0 + k;
   } else {
-    const uint32_t tiles = (static_cast<uint32_t>(d0) + kTile - 1) / kTile;
+    constexpr uint32_t T = TileCfg<kSssp>::kEdges;
+    const uint32_t tiles = (static_cast<uint32_t>(d0) + T - 1) / T;
     for (uint32_t t = gid; t < tiles; t += stride) a.fr[0].tile_node[t] = 0;
   }
   if (gid == 0) {
@@ -123,30 +177,63 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
     a.ctl->levels = 0u;
     a.ctl->frontier_entries = 0ull;
     a.ctl->edges_scanned = 0ull;
-    a.ctl->updates = 0ull;
   }
+  if (gid < kXcds * 16) a.ctl->xstat[gid / 16][gid % 16] = 0ull;
+}
+
+// SSSP epilogue: once the worklist of level L is empty, copy the distances
+// out of the packed state.  Launched after every batch of levels; exits at
+// once while work remains, so the host needs no extra synchronisation.
+__global__ __launch_bounds__(kBlock) void k_sssp_finish(KArgs a, uint32_t L) {
+  const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  if (static_cast<uint32_t>(c) != 0u) return;
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += stride)
+    a.dist[v] = static_cast<uint32_t>(a.dstate[v] >> 32);
 }
 
 // ------------------------------------------------------ balanced (WD) ----
 // Workload decomposition (Section III-A): the E_f edges of worklist L are cut
-// into tiles of kTile consecutive edges; workgroup b takes tiles b, b + G, ...
-// Within a tile, the worklist entries that overlap it are staged in LDS
-// (their edge-space start, first arc and, for SSSP, current distance); a
-// bitmask of entry starts plus per-word popcount prefixes maps each edge slot
-// to its entry in O(1), so lane t of the block handles slots t, t + 256, ...
-// and consecutive lanes read consecutive arcs of the same node (coalesced),
-// however the degrees are distributed.  Hubs simply span many tiles and are
-// expanded by many workgroups at once.
+// into tiles of T = 64 x kItems consecutive edges, and global wavefront g
+// (of W) takes tiles g, g + W, ...  Within a tile, the worklist entries that
+// overlap it are staged in the wavefront's LDS (one word per entry: the arc
+// index of the tile's first slot if the entry covered it, plus the entry's
+// current distance for SSSP); a bitmask of entry starts with per-word
+// popcount prefixes maps each edge slot to its entry in O(1).  Lane l handles
+// slots l, l + 64, ..., so the lanes read consecutive arcs of the same node
+// (coalesced) whatever the degree distribution; hubs simply span many tiles
+// and are expanded by many wavefronts at once.
+//
+// The kernel is latency-bound unless each round trip carries many
+// independent requests, and a workgroup-wide barrier per tile would make
+// every tile wait for its slowest wavefront.  So wavefronts run their tiles
+// independently (no barrier inside the loop), every phase issues all of a
+// lane's kItems loads (or atomics) before consuming any, the next tile's
+// start entry is fetched one tile ahead, and discoveries go to per-wave LDS
+// queues whose degree reads happen in bulk at flush time.
 template <bool kSssp>
+struct WaveLds {
+  static constexpr uint32_t T = TileCfg<kSssp>::kEdges;
+  uint32_t base[T];
+  uint32_t du[kSssp ? T : 1];
+  uint32_t flag[T / 32];
+  uint32_t wpre[T / 32];
+  int32_t qv[kWQ];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <bool kSssp, bool kNarrow>
 __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
-  __shared__ uint32_t sP[kTile];
-  __shared__ int32_t sS[kTile];
-  __shared__ uint32_t sD[kSssp ? kTile : 1];
-  __shared__ uint32_t sFlag[kTile / 32];
-  __shared__ uint32_t sWpre[kTile / 32];
-  __shared__ int32_t qS[kWaves][kQueue];
-  __shared__ int32_t qD[kWaves][kQueue];
-  __shared__ int32_t qV[kSssp ? kWaves : 1][kQueue];
+  constexpr int kItems = TileCfg<kSssp>::kItems;
+  constexpr uint32_t T = TileCfg<kSssp>::kEdges;
+  __shared__ WaveLds<kSssp> lds[kWaves];
+  __shared__ uint32_t merge[2 * kWaves];
+  __shared__ unsigned long long merge_base;
 
   const unsigned long long c = level_begin(a, L);
   const uint32_t Ef = static_cast<uint32_t>(c);
@@ -159,86 +246,187 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
   const Frontier cur = a.fr[L & 1];
   const Frontier nxt = a.fr[(L + 1) & 1];
   const int nctr = (L + 1) % 3;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wid = threadIdx.x >> 6;
+  WaveLds<kSssp>& w = lds[wid];
+  uint32_t* fx = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
+  const uint32_t* seen_cur = a.seen[L & 1];
+  uint32_t* seen_nxt = a.seen[(L + 1) & 1];
+  // SSSP compares against the distance half of the packed state only
+  const uint32_t* dist_hi = reinterpret_cast<const uint32_t*>(a.dstate) + 1;
+  uint32_t upd = 0, atom = 0, qcount = 0;
+  if (!kSssp) refresh_seen(a, L);
 
-  const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & 63;
-  const uint32_t wid = tid >> 6;
-  WaveQueue<kSssp> q{qS[wid], qD[wid], qV[kSssp ? wid : 0], 0u};
-  auto flush = [&]() { q.template flush_nodes<true>(a, nxt, nctr); };
-  uint32_t upd = 0;
-
-  const uint32_t ntiles = (Ef + kTile - 1) / kTile;
-  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint32_t t0 = tile * kTile;
-    const uint32_t t1 = min(t0 + static_cast<uint32_t>(kTile), Ef);
-    const uint32_t i0 = static_cast<uint32_t>(cur.tile_node[tile]);
-    if (i0 >= nf) {  // block-uniform; cannot happen when every tile was marked
-      if (tid == 0) atomicOr(&a.ctl->error, kErrBadTile);
+  const uint32_t ntiles = (Ef + T - 1) / T;
+  const uint32_t W = gridDim.x * kWaves;
+  uint32_t tile = blockIdx.x * kWaves + wid;
+  uint32_t i0_next = tile < ntiles ? static_cast<uint32_t>(*at<kNarrow>(cur.tile_node, tile)) : 0u;
+  for (; tile < ntiles; tile += W) {
+    const uint32_t i0 = i0_next;
+    if (tile + W < ntiles) i0_next = static_cast<uint32_t>(*at<kNarrow>(cur.tile_node, tile + W));
+    const uint32_t t0 = tile * T;
+    const uint32_t t1 = min(t0 + T, Ef);
+    if (i0 >= nf) {  // wave-uniform; cannot happen when every tile was marked
+      if (lane == 0) atomicOr(&a.ctl->error, kErrBadTile);
       continue;
     }
-    for (uint32_t k = tid; k < kTile / 32; k += kBlock) sFlag[k] = 0u;
-    __syncthreads();
+    if (lane < T / 32) w.flag[lane] = 0u;
+    wave_sync();
     // Stage the entries overlapping [t0, t1): a contiguous run starting at i0
-    // of at most kTile entries (each holds >= 1 edge).
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t j = r * kBlock + tid;
+    // of at most T entries (each holds >= 1 edge).  An entry's reads are
+    // issued together.
+    for (uint32_t j = lane; j < T; j += 64) {
       const uint32_t i = i0 + j;
-      int valid = 0;
+      bool valid = false;
       if (i < nf) {
-        const uint32_t p = cur.eprefix[i];
+        const uint32_t p = *at<kNarrow>(cur.eprefix, i);
+        const uint32_t st = static_cast<uint32_t>(*at<kNarrow>(cur.estart, i));
+        const int32_t node = kSssp ? *at<kNarrow>(cur.node, i) : 0;
         if (p < t1) {
-          valid = 1;
-          sP[j] = p;
-          sS[j] = cur.estart[i];
-          if (kSssp) sD[j] = a.dist[cur.node[i]];
+          valid = true;
+          w.base[j] = st + t0 - p;  // arc of slot s is base + s (mod 2^32)
+          if (kSssp) w.du[j] = *at<kNarrow>(dist_hi, 2u * static_cast<uint32_t>(node));
           const uint32_t s = (p > t0 ? p : t0) - t0;
-          atomicOr(&sFlag[s >> 5], 1u << (s & 31));
+          atomicOr(&w.flag[s >> 5], 1u << (s & 31));
         }
       }
-      if (!__syncthreads_or(valid)) break;
+      if (!__any(valid)) break;
     }
-    if (wid == 0) {
-      const uint32_t x = lane < kTile / 32 ? __popc(sFlag[lane]) : 0u;
+    wave_sync();
+    {
+      const uint32_t x = lane < T / 32 ? __popc(w.flag[lane]) : 0u;
       const uint32_t inc = wave_incl_scan(x);
-      if (lane < kTile / 32) sWpre[lane] = inc - x;
+      if (lane < T / 32) w.wpre[lane] = inc - x;
     }
-    __syncthreads();
+    wave_sync();
 
+    // Phase A: the arcs of this lane's kItems slots.
+    bool bad = false;  // malformed CSR (see lbg_validate_csr): flagged, arc skipped
     int32_t vv[kItems];
     uint32_t ww[kItems];
     uint32_t du[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-      const uint32_t j = t0 + r * kBlock + tid;
+      const uint32_t s = r * 64 + lane;
       vv[r] = -1;
-      if (j < t1) {
-        const uint32_t s = j - t0;
-        const uint32_t w = s >> 5;
+      ww[r] = 0;
+      du[r] = 0;
+      if (t0 + s < t1) {
+        const uint32_t k = s >> 5;
         const uint32_t msk = static_cast<uint32_t>((2ull << (s & 31)) - 1ull);
-        const int slot = static_cast<int>(sWpre[w] + __popc(sFlag[w] & msk)) - 1;
-        const uint32_t e = slot >= 0 ? static_cast<uint32_t>(sS[slot]) + (j - sP[slot]) : a.m;
+        const int slot = static_cast<int>(w.wpre[k] + __popc(w.flag[k] & msk)) - 1;
+        const uint32_t e = slot >= 0 ? w.base[slot] + s : a.m;
         if (e < a.m) {
-          vv[r] = a.cols[e];
+          vv[r] = *at<kNarrow>(a.cols, e);
           if (kSssp) {
-            ww[r] = a.weights[e];
-            du[r] = sD[slot];
+            ww[r] = *at<kNarrow>(a.weights, e);
+            du[r] = w.du[slot];
           }
         } else {
-          atomicOr(&a.ctl->error, kErrBadArc);
+          bad = true;
         }
       }
     }
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-      int32_t s = 0, d = 0;
-      const bool want = vv[r] >= 0 && relax<kSssp>(a, L, vv[r], kSssp ? du[r] : 0u,
-                                                   kSssp ? ww[r] : 0u, &upd, &s, &d);
-      q.push(want, s, d, vv[r], flush);
+      if (vv[r] >= 0 && static_cast<uint32_t>(vv[r]) >= a.n) {  // malformed cols
+        bad = true;
+        vv[r] = -1;
+      }
     }
-    __syncthreads();  // LDS descriptors are rewritten by the next tile
+    bool push[kItems];
+    if (!kSssp) {
+      // Phase B: visited words; phase C: this XCD's advisory filter; phase D:
+      // one atomic per surviving candidate.
+      uint32_t x[kItems];
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) x[r] = vv[r] >= 0 ? *at<kNarrow>(seen_cur, static_cast<uint32_t>(vv[r]) >> 5) : ~0u;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r)
+        x[r] = (vv[r] >= 0 && !(x[r] & (1u << (vv[r] & 31)))) ? *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) : ~0u;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t bit = 1u << (vv[r] & 31);
+        const bool cand = vv[r] >= 0 && !(x[r] & bit);
+        if (cand) {
+          *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) = x[r] | bit;  // plain store: a lost bit costs one more atomic
+          ++atom;
+          x[r] = atomicOr(at<kNarrow>(a.visited, static_cast<uint32_t>(vv[r]) >> 5), bit);
+        } else {
+          x[r] = ~0u;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        push[r] = vv[r] >= 0 && !(x[r] & (1u << (vv[r] & 31)));
+        if (push[r]) {
+          *at<kNarrow>(a.levels, vv[r]) = static_cast<int32_t>(L + 1);
+          uint32_t* sw = at<kNarrow>(seen_nxt, static_cast<uint32_t>(vv[r]) >> 5);
+          *sw |= 1u << (vv[r] & 31);  // a lost bit only costs an atomic later
+          ++upd;
+        }
+      }
+    } else {
+      // Phase B: current distances; phase C: one 64-bit atomicMin per
+      // improving arc, returning both the old distance and whether the node
+      // is already queued for this iteration.
+      uint32_t cd[kItems];
+#pragma unroll
+      for (int r = 0; r < kItems; ++r)
+        cd[r] = vv[r] >= 0 ? *at<kNarrow>(dist_hi, 2u * static_cast<uint32_t>(vv[r])) : 0u;
+      unsigned long long old[kItems];
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t alt = du[r] + ww[r];
+        old[r] = 0ull;
+        if (vv[r] >= 0 && alt < cd[r]) {
+          ++atom;
+          old[r] = atomicMin(at<kNarrow>(a.dstate, vv[r]),
+                             (static_cast<unsigned long long>(alt) << 32) | (L + 1));
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t alt = du[r] + ww[r];
+        const bool better = vv[r] >= 0 && alt < static_cast<uint32_t>(old[r] >> 32);
+        upd += better ? 1u : 0u;
+        push[r] = better && static_cast<uint32_t>(old[r]) != L + 1;
+      }
+    }
+    if (__any(bad) && lane == 0) atomicOr(&a.ctl->error, kErrBadArc);
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) wq_push<kSssp, T, kNarrow>(a, w.qv, qcount, push[r], vv[r], nxt, nctr);
+    if (qcount >= kWQ / 2) {
+      WaveFlush<kSssp, T, kNarrow> f;
+      f.flush(a, w.qv, qcount, nxt, nctr);
+      qcount = 0;
+    }
+    wave_sync();
   }
-  flush();
-  add_updates(a, upd);
+
+  // Final flush: one reservation for the whole workgroup.
+  WaveFlush<kSssp, T, kNarrow> f;
+  f.prepare(a, w.qv, qcount);
+  if (lane == 0) {
+    merge[wid] = f.tot_n;
+    merge[kWaves + wid] = f.tot_e;
+  }
+  __syncthreads();
+  uint32_t pn = 0, pe = 0, tn = 0, te = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    if (static_cast<uint32_t>(k) < wid) {
+      pn += merge[k];
+      pe += merge[kWaves + k];
+    }
+    tn += merge[k];
+    te += merge[kWaves + k];
+  }
+  if (threadIdx.x == 0)
+    merge_base = tn ? atomicAdd(&a.ctl->ctr[nctr], (static_cast<unsigned long long>(tn) << 32) | te) : 0ull;
+  __syncthreads();
+  f.write(a, nxt, static_cast<uint32_t>(merge_base >> 32) + pn, static_cast<uint32_t>(merge_base) + pe);
+  add_stats(a, upd, atom);
 }
 
 // ---------------------------------------------------------- node (BS) ----
@@ -259,6 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_node(KArgs a, uint32_t L) {
     if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrNodeCap);
     return;
   }
+  if (!kSssp) refresh_seen(a, L);
   const Frontier cur = a.fr[L & 1];
   const Frontier nxt = a.fr[(L + 1) & 1];
   const int nctr = (L + 1) % 3;
@@ -266,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_node(KArgs a, uint32_t L) {
   const uint32_t wid = tid >> 6;
   WaveQueue<kSssp> q{qS[wid], qD[wid], qV[kSssp ? wid : 0], 0u};
   auto flush = [&]() { q.template flush_nodes<false>(a, nxt, nctr); };
-  uint32_t upd = 0;
+  uint32_t upd = 0, atom = 0;
 
   for (uint32_t base = blockIdx.x * kBlock; base < nf; base += gridDim.x * kBlock) {
     const uint32_t i = base + tid;
@@ -281,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_node(KArgs a, uint32_t L) {
         atomicOr(&a.ctl->error, kErrBadArc);
         deg = 0;
       }
-      if (kSssp) du = a.dist[cur.node[i]];
+      if (kSssp) du = static_cast<uint32_t>(a.dstate[cur.node[i]] >> 32);
     }
     const int32_t dmax = wave_max(deg);
     for (int32_t k = 0; k < dmax; ++k) {
@@ -290,13 +479,13 @@ __global__ __launch_bounds__(kBlock) void k_expand_node(KArgs a, uint32_t L) {
       if (k < deg) {
         const int32_t e = s0 + k;
         v = a.cols[e];
-        want = relax<kSssp>(a, L, v, du, kSssp ? a.weights[e] : 0u, &upd, &s, &d);
+        want = relax<kSssp>(a, L, v, du, kSssp ? a.weights[e] : 0u, &upd, &atom, &s, &d);
       }
       q.push(want, s, d, v, flush);
     }
   }
   flush();
-  add_updates(a, upd);
+  add_stats(a, upd, atom);
 }
 
 // ---------------------------------------------------------- edge (EP) ----
@@ -316,6 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_edge(KArgs a, uint32_t L) {
     if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrEdgeCap);
     return;
   }
+  if (!kSssp) refresh_seen(a, L);
   const int32_t* wl = a.fr[L & 1].node;
   int32_t* nwl = a.fr[(L + 1) & 1].node;
   const int nctr = (L + 1) % 3;
@@ -323,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_edge(KArgs a, uint32_t L) {
   const uint32_t wid = tid >> 6;
   WaveQueue<false> q{qS[wid], qD[wid], nullptr, 0u};
   auto flush = [&]() { q.flush_edges(a, nwl, nctr); };
-  uint32_t upd = 0;
+  uint32_t upd = 0, atom = 0;
 
   for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
     const uint32_t i = base + tid;
@@ -334,15 +524,15 @@ __global__ __launch_bounds__(kBlock) void k_expand_edge(KArgs a, uint32_t L) {
       const int32_t v = static_cast<uint32_t>(e) < a.m ? a.cols[e] : -1;
       uint32_t du = 0, w = 0;
       if (kSssp) {
-        du = a.dist[a.coo_src[e]];
+        du = static_cast<uint32_t>(a.dstate[a.coo_src[e]] >> 32);
         w = a.weights[e];
       }
-      want = relax<kSssp>(a, L, v, du, w, &upd, &s, &d);
+      want = relax<kSssp>(a, L, v, du, w, &upd, &atom, &s, &d);
     }
     q.push(want, s, d, 0, flush);
   }
   flush();
-  add_updates(a, upd);
+  add_stats(a, upd, atom);
 }
 
 // ------------------------------------------------------- CSR validation --

@@ -31,7 +31,7 @@ class LbgError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("frontier_entries", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
-                ("updates", ctypes.c_int64)]
+                ("updates", ctypes.c_int64), ("atomics", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -41,7 +41,8 @@ class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("empty_launches", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("empty_ms", ctypes.c_double),
                 ("frontier_entries", ctypes.c_int64),
-                ("edges_scanned", ctypes.c_int64), ("updates", ctypes.c_int64)]
+                ("edges_scanned", ctypes.c_int64), ("updates", ctypes.c_int64),
+                ("atomics", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

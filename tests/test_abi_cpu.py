@@ -34,18 +34,21 @@ def test_workspace_formulas():
     assert T > 0 and T % 256 == 0
     al = lambda x: (x + 255) // 256 * 256
     n, m = 1000, 123457
-    ctl = 256
-    # BFS, node-based / balanced: visited bitmap + 2 x (3 node arrays + tile marks)
+    ctl = al(128 + 8 * 128)
+    words = (n + 31) // 32
+    bfs_state = 3 * al(4 * words) + al(4 * words * 8)   # visited + 2 snapshots + per-XCD filters
+    sssp_state = al(8 * n)                          # packed (distance, iteration)
+    # BFS, node-based / balanced: node state + 2 x (3 node arrays + tile marks)
     tiles = (m + T - 1) // T + 2
-    exp_bfs = ctl + al(4 * ((n + 31) // 32)) + 2 * (3 * al(4 * n) + al(4 * tiles))
+    exp_bfs = ctl + bfs_state + 2 * (3 * al(4 * n) + al(4 * tiles))
     assert lbgmod.workspace_bytes(n, m, "balanced", False) == exp_bfs
     assert lbgmod.workspace_bytes(n, m, "node", False) == exp_bfs
     assert lbgmod.workspace_bytes(n, m, "auto", False) == exp_bfs
-    exp_sssp = ctl + al(4 * n) + 2 * (3 * al(4 * n) + al(4 * tiles))
+    exp_sssp = ctl + sssp_state + 2 * (3 * al(4 * n) + al(4 * tiles))
     assert lbgmod.workspace_bytes(n, m, "balanced", True) == exp_sssp
     # edge-based: two worklists of m arc ids (the COO-scale cost, Section II-B)
-    assert lbgmod.workspace_bytes(n, m, "edge", False) == ctl + al(4 * ((n + 31) // 32)) + 2 * al(4 * m)
-    assert lbgmod.workspace_bytes(n, m, "edge", True) == ctl + al(4 * n) + 2 * al(4 * m)
+    assert lbgmod.workspace_bytes(n, m, "edge", False) == ctl + bfs_state + 2 * al(4 * m)
+    assert lbgmod.workspace_bytes(n, m, "edge", True) == ctl + sssp_state + 2 * al(4 * m)
     # CSR strategies stay O(n + m / tile); the edge one grows with m
     assert lbgmod.workspace_bytes(n, 50 * m, "balanced", False) < lbgmod.workspace_bytes(n, 50 * m, "edge", False) / 10
     # invalid arguments

@@ -187,3 +187,20 @@ def test_grid2048_full():
     dh = _dev(h)
     s = int(srcs[1])
     assert np.array_equal(_gpu_bfs(dh, s, "balanced"), O.bfs(h.offsets, h.cols, s))
+
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_workspace_reuse_across_sources(strat):
+    """Back-to-back solves from different sources share one workspace: no
+    state of an earlier solve (visited snapshots, filters, stamps) may leak
+    into a later one.  A directed graph where the sources reach nested sets
+    makes any leaked 'already visited' bit change a level."""
+    g = graphgen.uniform(12, k=3)
+    dg = _dev(g)
+    ws = lbg.Workspace("cuda")
+    srcs = [0, 1, 2, 3, 0, 5, 0]
+    for s in srcs:
+        lv = lbg.bfs(dg, s, strategy=strat, workspace=ws).cpu().numpy()
+        assert np.array_equal(lv, O.bfs(g.offsets, g.cols, s)), f"bfs src={s}"
+        d = lbg.sssp(dg, s, strategy=strat, workspace=ws).cpu().numpy().view(np.uint32)
+        assert np.array_equal(d, O.dijkstra(g.offsets, g.cols, g.weights, s)), f"sssp src={s}"
