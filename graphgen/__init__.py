@@ -174,6 +174,47 @@ def from_edges(n: int, src, dst, weights=None, name: str = "edges") -> Graph:
     return Graph(name, off.astype(np.int32), dst[order].astype(np.int32), w[order])
 
 
+def pack(graphs) -> tuple:
+    """Disjoint union of several graphs in one CSR with global node ids.
+    Returns (union Graph, node_base int64[k+1], edge_base int64[k+1]);
+    instance i owns nodes [node_base[i], node_base[i+1])."""
+    nb = np.zeros(len(graphs) + 1, dtype=np.int64)
+    eb = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        nb[i + 1] = nb[i] + g.n
+        eb[i + 1] = eb[i] + g.m
+    if nb[-1] >= 2**31 or eb[-1] >= 2**31:
+        raise ValueError("packed graph exceeds int32 ids")
+    off = np.empty(nb[-1] + 1, dtype=np.int64)
+    off[-1] = eb[-1]
+    cols = np.empty(eb[-1], dtype=np.int32)
+    w = np.empty(eb[-1], dtype=np.uint32)
+    for i, g in enumerate(graphs):
+        off[nb[i]: nb[i + 1]] = g.offsets[:-1].astype(np.int64) + eb[i]
+        cols[eb[i]: eb[i + 1]] = g.cols.astype(np.int64) + nb[i]
+        w[eb[i]: eb[i + 1]] = g.weights
+    return Graph("packed", off.astype(np.int32), cols, w), nb, eb
+
+
+def batch_instances(count: int = 256, salt: int = 0, lo_exp: int = 10, hi_exp: int = 18):
+    """The batched workload: `count` instances of uneven size, half R-MAT
+    (scale uniform in [lo_exp, hi_exp], edge factor 16, symmetrised) and half
+    uniform (n = floor(2^U(lo_exp, hi_exp)), 8 out-arcs per node), weights
+    U[1,255]; instance sizes come from stream 0 of the batched family."""
+    seed = stream_seed(FAMILY_BATCH, STREAM_STRUCT, salt)
+    graphs = []
+    for i in range(count):
+        x = splitmix_at(seed, i)
+        if i % 2 == 0:
+            scale = lo_exp + (x % (hi_exp - lo_exp + 1))
+            graphs.append(rmat(scale, edge_factor=16, wlo=1, whi=255, salt=salt * 1000 + i + 1))
+        else:
+            u = (x >> 11) / float(1 << 53)
+            n = int(2.0 ** (lo_exp + u * (hi_exp - lo_exp)))
+            graphs.append(uniform(k=8, wlo=1, whi=255, salt=salt * 1000 + i + 1, n=n))
+    return graphs
+
+
 def splitmix_at(seed: int, i: int) -> int:
     return int(_load().gg_splitmix_at(seed, i))
 

@@ -58,7 +58,8 @@ typedef enum {
   LBG_ENOMEM = -3,     /* workspace smaller than lbg_workspace_bytes() */
   LBG_EHIP = -4,       /* a HIP runtime call or kernel launch failed */
   LBG_EOVERFLOW = -5,  /* device-side capacity guard tripped (library bug) */
-  LBG_EINTERNAL = -6   /* level count exceeded n + 1 (library bug or bad CSR) */
+  LBG_EINTERNAL = -6,  /* level count exceeded n + 1 (library bug or bad CSR) */
+  LBG_EBUSY = -7       /* engine: no free query slot */
 } lbg_status;
 
 typedef enum {
@@ -140,8 +141,99 @@ typedef struct {
   int64_t atomics;           /* device-scope atomics issued on node state */
 } lbg_profile;
 
-/* Totals of BFS (is_sssp = 0) or SSSP (is_sssp = 1) solves since the last reset. */
-void lbg_profile_read(int32_t is_sssp, lbg_profile* out);
+/* Totals since the last reset of BFS solves (which = 0), SSSP solves (1) or
+ * batched solves (2). */
+void lbg_profile_read(int32_t which, lbg_profile* out);
+
+/* ------------------------------------------------------------------------
+ * Batched solves.  Many independent BFS/SSSP queries advance level by level
+ * through ONE shared worklist whose entries carry their query, so a batch
+ * costs one launch per level however many queries it holds, and the work of
+ * small and large queries is balanced together (the edge-tile split of the
+ * balanced strategy, over the union of all queries' frontiers).
+ *
+ * The graph is a disjoint union of instances in one CSR with global node
+ * ids: instance k owns the node range [lo, hi) and every arc leaving a node
+ * of that range lands in it (pack instances by offsetting their ids).  A BFS
+ * query is computed as a unit-weight relaxation (the same least fixed point),
+ * so BFS and SSSP queries mix freely in one batch.
+ * ------------------------------------------------------------------------ */
+#define LBG_KIND_BFS 0
+#define LBG_KIND_SSSP 1
+
+typedef struct {
+  int32_t src;     /* global source node, lo <= src < hi */
+  int32_t lo, hi;  /* node range of the query's instance */
+  int32_t kind;    /* LBG_KIND_BFS or LBG_KIND_SSSP */
+  int64_t out_off; /* first element of the query's result row in `out` */
+} lbg_query;
+
+/* Device workspace for lbg_batch_solve (0 for invalid arguments). */
+size_t lbg_batch_workspace_bytes(int32_t num_queries, int64_t total_rows, int64_t total_arcs);
+
+/* Solves num_queries queries (a HOST array) over the packed graph.  Query q
+ * writes hi - lo results to out[out_off .. out_off + hi - lo): int32 levels
+ * (INT32_MAX = unreachable) for BFS, uint32 distances (UINT32_MAX) for SSSP,
+ * element j for node lo + j.  Rows must not overlap; total_rows (< 2^31) is
+ * the length of `out` (device uint32, int32 bit patterns for BFS rows).
+ * total_arcs bounds the edge space of one level: the sum over queries of the
+ * arcs leaving their instance (< 2^32).  weights are required (BFS queries
+ * ignore them).  Errors as for lbg_bfs; an arc leaving its instance makes the
+ * call return LBG_EOVERFLOW instead of touching another row.  The call is
+ * stream-ordered and returns when all queries have finished. */
+int lbg_batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, const lbg_query* queries, int32_t num_queries, uint32_t* out,
+                    int64_t total_rows, int64_t total_arcs, void* workspace, size_t workspace_bytes,
+                    lbg_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Engine: continuous batching for serving.  An engine keeps one packed graph
+ * (as for lbg_batch_solve) and a pool of query slots; queries submitted
+ * while others are in flight join the shared worklist at the next level
+ * boundary, finished queries leave, and their slots and rows can be reused.
+ * A query's result is the same whatever else runs with it: the relaxation
+ * reaches the same least fixed point in any order.
+ *
+ * The caller owns the graph, the result rows (`rows_out`, device uint32[max_rows],
+ * one row per query at the query's out_off) and the workspace; it chooses
+ * each query's row (admission by memory footprint is the caller's policy).
+ * All calls on one engine must come from one thread; work is ordered on the
+ * engine's stream and every call returns with its work finished.
+ * ------------------------------------------------------------------------ */
+typedef struct lbg_engine lbg_engine;
+
+/* Device workspace for an engine with these capacities (0 if invalid).
+ * max_rows: total result elements of concurrently admitted queries (< 2^31);
+ * max_level_arcs: bound on the arcs one level can hold (< 2^32), e.g. the sum
+ * of the arc counts of the instances that may be queried concurrently. */
+size_t lbg_engine_workspace_bytes(int32_t max_queries, int64_t max_rows, int64_t max_level_arcs);
+
+int lbg_engine_create(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
+                      int32_t n, int64_t m, int32_t max_queries, int64_t max_rows,
+                      int64_t max_level_arcs, uint32_t* rows_out, void* workspace,
+                      size_t workspace_bytes, void* stream, lbg_engine** engine);
+
+/* Queue a query (host struct; out_off = its row in rows_out).  It joins the
+ * batch at the next lbg_engine_step.  *slot receives its slot; LBG_EBUSY if
+ * every slot is in use. */
+int lbg_engine_submit(lbg_engine* e, const lbg_query* q, int32_t* slot);
+
+/* Inject queued queries, expand `levels` levels, then detect queries whose
+ * worklist emptied and write their rows.  *finished (nullable) receives how
+ * many finished in this step; lbg_engine_finished lists them. */
+int lbg_engine_step(lbg_engine* e, int32_t levels, int32_t* finished);
+
+/* Slots that finished in the last step (their rows in rows_out are final).
+ * Returns how many were written to `slots`. */
+int32_t lbg_engine_finished(const lbg_engine* e, int32_t* slots, int32_t max_slots);
+
+/* Return a finished slot to the pool (its row may then be reused). */
+int lbg_engine_release(lbg_engine* e, int32_t slot);
+
+/* Cumulative stats, number of queued + running queries, next level index. */
+int lbg_engine_info(const lbg_engine* e, lbg_stats* stats, int32_t* running, uint32_t* level);
+
+void lbg_engine_destroy(lbg_engine* e);
 
 /* Tile of edges one workgroup of the balanced expansion processes (the
  * granularity of the workload decomposition), and the persistent grid size

@@ -114,7 +114,7 @@ int resident_grid(K kernel) {
 }
 
 struct Grids {
-  int bal[2][2], node[2], edge[2];  // bal[is_sssp][narrow]
+  int bal[2][2], node[2], edge[2], multi[2];  // bal[is_sssp][narrow], multi[narrow]
 };
 
 const Grids& grids() {
@@ -133,6 +133,8 @@ const Grids& grids() {
     g[dev].node[1] = resident_grid(lbg::k_expand_node<true>);
     g[dev].edge[0] = resident_grid(lbg::k_expand_edge<false>);
     g[dev].edge[1] = resident_grid(lbg::k_expand_edge<true>);
+    g[dev].multi[0] = resident_grid(lbg::k_expand_balanced<true, false, true>);
+    g[dev].multi[1] = resident_grid(lbg::k_expand_balanced<true, true, true>);
     done[dev] = true;
   }
   return g[dev];
@@ -143,7 +145,7 @@ int grid_blocks() { return grids().bal[0][1]; }
 // Host side of the profiling counters (see lbg_profile_enable).
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-lbg_profile g_prof[2]{};  // [is_sssp]
+lbg_profile g_prof[3]{};  // [0] BFS, [1] SSSP, [2] batched solves
 
 struct PinnedCtl {
   Ctl* p = nullptr;
@@ -366,6 +368,444 @@ int solve(const Problem& P) {
   return LBG_OK;
 }
 
+
+// ----------------------------------------------------------------- batch --
+struct BatchLayout {
+  size_t ctl, qtab, dstate, node[2], qid[2], eprefix[2], estart[2], tile[2], total;
+  uint32_t node_cap, tile_cap;
+};
+
+BatchLayout batch_layout(int32_t num_queries, int64_t rows, int64_t total_arcs) {
+  BatchLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  L.ctl = take(sizeof(Ctl));
+  L.qtab = take(sizeof(lbg::QInfo) * static_cast<size_t>(num_queries));
+  L.dstate = take(sizeof(unsigned long long) * static_cast<size_t>(rows));
+  L.node_cap = static_cast<uint32_t>(rows);
+  L.tile_cap = static_cast<uint32_t>((total_arcs + lbg::kMultiTile - 1) / lbg::kMultiTile + 2);
+  for (int b = 0; b < 2; ++b) {
+    L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(rows));
+    L.qid[b] = take(sizeof(int32_t) * static_cast<size_t>(rows));
+    L.eprefix[b] = take(sizeof(uint32_t) * static_cast<size_t>(rows));
+    L.estart[b] = take(sizeof(int32_t) * static_cast<size_t>(rows));
+    L.tile[b] = take(sizeof(int32_t) * static_cast<size_t>(L.tile_cap));
+  }
+  L.total = off;
+  return L;
+}
+
+int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                int64_t m, const lbg_query* queries, int32_t num_queries, uint32_t* out,
+                int64_t rows, int64_t total_arcs, void* workspace, size_t workspace_bytes,
+                lbg_stats* stats, hipStream_t st) {
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX)
+    return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
+  if (num_queries <= 0 || !queries) return fail(LBG_EINVAL, "need at least one query");
+  if (rows <= 0 || rows > INT32_MAX)
+    return fail(LBG_ERANGE, "total_rows must be in [1, INT32_MAX] (got %lld)", static_cast<long long>(rows));
+  if (total_arcs < 0 || total_arcs > UINT32_MAX)
+    return fail(LBG_ERANGE, "total_arcs must be in [0, 2^32)");
+  if (!offsets || !out || !workspace || (m > 0 && (!cols || !weights)))
+    return fail(LBG_EINVAL, "null offsets/cols/weights/output/workspace pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  const BatchLayout Lay = batch_layout(num_queries, rows, total_arcs);
+  if (workspace_bytes < Lay.total)
+    return fail(LBG_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, Lay.total);
+  std::vector<lbg::QInfo> qt(static_cast<size_t>(num_queries));
+  for (int32_t q = 0; q < num_queries; ++q) {
+    const lbg_query& Q = queries[q];
+    if (Q.lo < 0 || Q.hi > n || Q.lo >= Q.hi || Q.src < Q.lo || Q.src >= Q.hi)
+      return fail(LBG_ERANGE, "query %d: need 0 <= lo <= src < hi <= n", q);
+    if (Q.kind != LBG_KIND_BFS && Q.kind != LBG_KIND_SSSP)
+      return fail(LBG_EINVAL, "query %d: unknown kind %d", q, Q.kind);
+    if (Q.out_off < 0 || Q.out_off + (Q.hi - Q.lo) > rows)
+      return fail(LBG_ERANGE, "query %d: result row outside [0, total_rows)", q);
+    lbg::QInfo& I = qt[static_cast<size_t>(q)];
+    I.row_start = static_cast<int32_t>(Q.out_off);
+    I.row_len = Q.hi - Q.lo;
+    I.delta = I.row_start - Q.lo;
+    I.kind = Q.kind;
+    I.src = Q.src;
+    I.pad[0] = I.pad[1] = I.pad[2] = 0;
+  }
+
+  char* ws = static_cast<char*>(workspace);
+  KArgs a{};
+  a.offsets = offsets;
+  a.cols = cols;
+  a.weights = weights;
+  a.dist = out;
+  a.dstate = reinterpret_cast<unsigned long long*>(ws + Lay.dstate);
+  for (int b = 0; b < 2; ++b) {
+    a.fr[b].node = reinterpret_cast<int32_t*>(ws + Lay.node[b]);
+    a.fr[b].qid = reinterpret_cast<int32_t*>(ws + Lay.qid[b]);
+    a.fr[b].eprefix = reinterpret_cast<uint32_t*>(ws + Lay.eprefix[b]);
+    a.fr[b].estart = reinterpret_cast<int32_t*>(ws + Lay.estart[b]);
+    a.fr[b].tile_node = reinterpret_cast<int32_t*>(ws + Lay.tile[b]);
+  }
+  a.ctl = reinterpret_cast<Ctl*>(ws + Lay.ctl);
+  a.qtab = reinterpret_cast<const lbg::QInfo*>(ws + Lay.qtab);
+  a.n = static_cast<uint32_t>(n);
+  a.m = static_cast<uint32_t>(m);
+  a.node_cap = Lay.node_cap;
+  a.tile_cap = Lay.tile_cap;
+  a.num_queries = static_cast<uint32_t>(num_queries);
+  a.rows = static_cast<uint32_t>(rows);
+  bool profiling;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    profiling = g_prof_on;
+  }
+  a.count_stats = (stats || profiling) ? 1u : 0u;
+  Ctl* host = pinned_ctl();
+  if (!host) return fail(LBG_EHIP, "hipHostMalloc of the readback word failed");
+
+  HIP_TRY(hipMemcpyAsync(ws + Lay.qtab, qt.data(), sizeof(lbg::QInfo) * qt.size(),
+                         hipMemcpyHostToDevice, st));
+  const bool narrow = n < (1 << 29) && m < (int64_t{1} << 30) && rows < (int64_t{1} << 29);
+  const Grids& GR = grids();
+  const int fill_blocks = std::min(num_queries, 4096);
+  const int seed_blocks = (num_queries + lbg::kBlock - 1) / lbg::kBlock;
+  const int fin_blocks = std::min(num_queries, 4096);
+  hipLaunchKernelGGL(lbg::k_batch_fill, dim3(fill_blocks), dim3(lbg::kBlock), 0, st, a);
+  if (narrow) hipLaunchKernelGGL(lbg::k_batch_seed<true>, dim3(seed_blocks), dim3(lbg::kBlock), 0, st, a);
+  else hipLaunchKernelGGL(lbg::k_batch_seed<false>, dim3(seed_blocks), dim3(lbg::kBlock), 0, st, a);
+  HIP_TRY(hipGetLastError());
+
+  uint32_t L = 0, batch = 8;
+  size_t nev = 0;
+  const uint64_t level_cap = static_cast<uint64_t>(rows) + 2;
+  for (;;) {
+    for (uint32_t k = 0; k < batch; ++k, ++L) {
+      if (profiling) {
+        hipEvent_t e = event_at(nev++);
+        if (!e) return fail(LBG_EHIP, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(e, st));
+      }
+      if (narrow)
+        hipLaunchKernelGGL((lbg::k_expand_balanced<true, true, true>), dim3(GR.multi[1]), dim3(lbg::kBlock), 0, st, a, L);
+      else
+        hipLaunchKernelGGL((lbg::k_expand_balanced<true, false, true>), dim3(GR.multi[0]), dim3(lbg::kBlock), 0, st, a, L);
+      HIP_TRY(hipGetLastError());
+      if (profiling) {
+        hipEvent_t e = event_at(nev++);
+        if (!e) return fail(LBG_EHIP, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(e, st));
+      }
+    }
+    hipLaunchKernelGGL(lbg::k_batch_finish, dim3(fin_blocks), dim3(lbg::kBlock), 0, st, a, L);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (host->error)
+      return fail(LBG_EOVERFLOW, "device capacity/bounds guard tripped (flags 0x%x)", host->error);
+    if (static_cast<uint32_t>(host->ctr[L % 3]) == 0u) break;
+    if (L > level_cap) return fail(LBG_EINTERNAL, "more levels than rows; malformed input?");
+    batch = std::min<uint32_t>(batch * 2, 64);
+  }
+  if (profiling) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    lbg_profile& gp = g_prof[2];
+    for (size_t k = 0; k + 1 < nev; k += 2) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, g_events[k], g_events[k + 1]));
+      if (k / 2 < host->levels) {
+        gp.launches += 1;
+        gp.kernel_ms += ms;
+      } else {
+        gp.empty_launches += 1;
+        gp.empty_ms += ms;
+      }
+    }
+    gp.frontier_entries += static_cast<int64_t>(host->frontier_entries);
+    gp.edges_scanned += static_cast<int64_t>(host->edges_scanned);
+    gp.updates += xsum(host, 0);
+    gp.atomics += xsum(host, 1);
+  }
+  if (stats) {
+    stats->levels = static_cast<int32_t>(host->levels);
+    stats->reserved = 0;
+    stats->frontier_entries = static_cast<int64_t>(host->frontier_entries);
+    stats->edges_scanned = static_cast<int64_t>(host->edges_scanned);
+    stats->updates = xsum(host, 0);
+    stats->atomics = xsum(host, 1);
+  }
+  return LBG_OK;
+}
+
+
+// ---------------------------------------------------------------- engine --
+struct EngineLayout {
+  BatchLayout b;
+  size_t qlast, slots, total;
+};
+
+EngineLayout engine_layout(int32_t max_queries, int64_t max_rows, int64_t max_level_arcs) {
+  EngineLayout E{};
+  E.b = batch_layout(max_queries, max_rows, max_level_arcs);
+  size_t off = E.b.total;
+  E.qlast = off;
+  off += align_up(sizeof(uint32_t) * static_cast<size_t>(max_queries));
+  E.slots = off;
+  off += align_up(sizeof(int32_t) * static_cast<size_t>(max_queries));
+  E.total = off;
+  return E;
+}
+
+}  // namespace
+
+struct lbg_engine {
+  KArgs a{};
+  hipStream_t st = nullptr;
+  int32_t max_q = 0;
+  int64_t max_rows = 0;
+  uint32_t L = 0;  // next level to expand
+  bool narrow = false;
+  char* ws = nullptr;
+  EngineLayout lay{};
+  std::vector<lbg::QInfo> qt;
+  std::vector<uint8_t> state;  // 0 free, 1 pending seed, 2 running, 3 finished (row written)
+  std::vector<int32_t> pending, done;
+  uint32_t* host_qlast = nullptr;  // pinned
+  int32_t* host_slots = nullptr;   // pinned
+  Ctl* host_ctl = nullptr;         // pinned
+  int64_t steps = 0;
+};
+
+namespace {
+
+int engine_sync_state(lbg_engine* e) {
+  HIP_TRY(hipMemcpyAsync(e->host_ctl, e->a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, e->st));
+  HIP_TRY(hipMemcpyAsync(e->host_qlast, e->ws + e->lay.qlast, sizeof(uint32_t) * e->max_q,
+                         hipMemcpyDeviceToHost, e->st));
+  HIP_TRY(hipStreamSynchronize(e->st));
+  if (e->host_ctl->error)
+    return fail(LBG_EOVERFLOW, "device capacity/bounds guard tripped (flags 0x%x)", e->host_ctl->error);
+  return LBG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbg_engine_workspace_bytes(int32_t max_queries, int64_t max_rows, int64_t max_level_arcs) {
+  if (max_queries <= 0 || max_rows <= 0 || max_rows > INT32_MAX || max_level_arcs < 0 ||
+      max_level_arcs > UINT32_MAX)
+    return 0;
+  return engine_layout(max_queries, max_rows, max_level_arcs).total;
+}
+
+int lbg_engine_create(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
+                      int32_t n, int64_t m, int32_t max_queries, int64_t max_rows,
+                      int64_t max_level_arcs, uint32_t* rows_out, void* workspace,
+                      size_t workspace_bytes, void* stream, lbg_engine** engine) {
+  if (!engine) return fail(LBG_EINVAL, "null engine handle");
+  *engine = nullptr;
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX) return fail(LBG_ERANGE, "m must be in [0, INT32_MAX]");
+  if (!offsets || !rows_out || !workspace || (m > 0 && (!cols || !weights)))
+    return fail(LBG_EINVAL, "null offsets/cols/weights/rows/workspace pointer");
+  const size_t need = lbg_engine_workspace_bytes(max_queries, max_rows, max_level_arcs);
+  if (need == 0) return fail(LBG_ERANGE, "invalid engine capacities");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  if (workspace_bytes < need)
+    return fail(LBG_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  lbg_engine* e = new lbg_engine();
+  e->st = static_cast<hipStream_t>(stream);
+  e->max_q = max_queries;
+  e->max_rows = max_rows;
+  e->lay = engine_layout(max_queries, max_rows, max_level_arcs);
+  e->ws = static_cast<char*>(workspace);
+  e->narrow = n < (1 << 29) && m < (int64_t{1} << 30) && max_rows < (int64_t{1} << 29);
+  e->qt.assign(static_cast<size_t>(max_queries), lbg::QInfo{});
+  e->state.assign(static_cast<size_t>(max_queries), 0);
+  void* p1 = nullptr;
+  void* p2 = nullptr;
+  void* p3 = nullptr;
+  if (hipHostMalloc(&p1, sizeof(uint32_t) * max_queries, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&p2, sizeof(int32_t) * max_queries, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&p3, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    if (p1) (void)hipHostFree(p1);
+    if (p2) (void)hipHostFree(p2);
+    if (p3) (void)hipHostFree(p3);
+    delete e;
+    return fail(LBG_EHIP, "hipHostMalloc failed");
+  }
+  e->host_qlast = static_cast<uint32_t*>(p1);
+  e->host_slots = static_cast<int32_t*>(p2);
+  e->host_ctl = static_cast<Ctl*>(p3);
+  const BatchLayout& Lay = e->lay.b;
+  KArgs& a = e->a;
+  a.offsets = offsets;
+  a.cols = cols;
+  a.weights = weights;
+  a.dist = rows_out;
+  a.dstate = reinterpret_cast<unsigned long long*>(e->ws + Lay.dstate);
+  for (int b = 0; b < 2; ++b) {
+    a.fr[b].node = reinterpret_cast<int32_t*>(e->ws + Lay.node[b]);
+    a.fr[b].qid = reinterpret_cast<int32_t*>(e->ws + Lay.qid[b]);
+    a.fr[b].eprefix = reinterpret_cast<uint32_t*>(e->ws + Lay.eprefix[b]);
+    a.fr[b].estart = reinterpret_cast<int32_t*>(e->ws + Lay.estart[b]);
+    a.fr[b].tile_node = reinterpret_cast<int32_t*>(e->ws + Lay.tile[b]);
+  }
+  a.ctl = reinterpret_cast<Ctl*>(e->ws + Lay.ctl);
+  a.qtab = reinterpret_cast<const lbg::QInfo*>(e->ws + Lay.qtab);
+  a.qlast = reinterpret_cast<uint32_t*>(e->ws + e->lay.qlast);
+  a.n = static_cast<uint32_t>(n);
+  a.m = static_cast<uint32_t>(m);
+  a.node_cap = Lay.node_cap;
+  a.tile_cap = Lay.tile_cap;
+  a.num_queries = static_cast<uint32_t>(max_queries);
+  a.rows = static_cast<uint32_t>(max_rows);
+  a.count_stats = 1u;
+  // clear the control block (counters of levels 0..2, stats) and qlast
+  if (hipMemsetAsync(a.ctl, 0, sizeof(Ctl), e->st) != hipSuccess ||
+      hipMemsetAsync(a.qlast, 0, sizeof(uint32_t) * max_queries, e->st) != hipSuccess ||
+      hipStreamSynchronize(e->st) != hipSuccess) {
+    lbg_engine_destroy(e);
+    return fail(LBG_EHIP, "engine initialisation failed");
+  }
+  *engine = e;
+  return LBG_OK;
+}
+
+int lbg_engine_submit(lbg_engine* e, const lbg_query* q, int32_t* slot) {
+  if (!e || !q || !slot) return fail(LBG_EINVAL, "null argument");
+  if (q->lo < 0 || q->hi > static_cast<int32_t>(e->a.n) || q->lo >= q->hi || q->src < q->lo ||
+      q->src >= q->hi)
+    return fail(LBG_ERANGE, "need 0 <= lo <= src < hi <= n");
+  if (q->kind != LBG_KIND_BFS && q->kind != LBG_KIND_SSSP)
+    return fail(LBG_EINVAL, "unknown kind %d", q->kind);
+  if (q->out_off < 0 || q->out_off + (q->hi - q->lo) > e->max_rows)
+    return fail(LBG_ERANGE, "result row outside [0, max_rows)");
+  int32_t s = -1;
+  for (int32_t k = 0; k < e->max_q; ++k)
+    if (e->state[static_cast<size_t>(k)] == 0) {
+      s = k;
+      break;
+    }
+  if (s < 0) return fail(LBG_EBUSY, "all %d query slots are in use", e->max_q);
+  lbg::QInfo& I = e->qt[static_cast<size_t>(s)];
+  I.row_start = static_cast<int32_t>(q->out_off);
+  I.row_len = q->hi - q->lo;
+  I.delta = I.row_start - q->lo;
+  I.kind = q->kind;
+  I.src = q->src;
+  I.pad[0] = I.pad[1] = I.pad[2] = 0;
+  e->state[static_cast<size_t>(s)] = 1;
+  e->pending.push_back(s);
+  *slot = s;
+  return LBG_OK;
+}
+
+int lbg_engine_step(lbg_engine* e, int32_t levels, int32_t* finished) {
+  if (!e || levels < 0) return fail(LBG_EINVAL, "bad arguments");
+  KArgs& a = e->a;
+  const hipStream_t st = e->st;
+  const Grids& GR = grids();
+  if (!e->pending.empty()) {
+    const int cnt = static_cast<int>(e->pending.size());
+    for (int k = 0; k < cnt; ++k) {
+      const int32_t s = e->pending[static_cast<size_t>(k)];
+      e->host_slots[k] = s;
+      HIP_TRY(hipMemcpyAsync(e->ws + e->lay.b.qtab + sizeof(lbg::QInfo) * s, &e->qt[static_cast<size_t>(s)],
+                             sizeof(lbg::QInfo), hipMemcpyHostToDevice, st));
+    }
+    int32_t* dslots = reinterpret_cast<int32_t*>(e->ws + e->lay.slots);
+    HIP_TRY(hipMemcpyAsync(dslots, e->host_slots, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(lbg::k_engine_fill, dim3(std::min(cnt, 4096)), dim3(lbg::kBlock), 0, st, a,
+                       static_cast<const int32_t*>(dslots), cnt);
+    const int sb = (cnt + lbg::kBlock - 1) / lbg::kBlock;
+    if (e->narrow) hipLaunchKernelGGL(lbg::k_engine_seed<true>, dim3(sb), dim3(lbg::kBlock), 0, st, a, static_cast<const int32_t*>(dslots), cnt, e->L);
+    else hipLaunchKernelGGL(lbg::k_engine_seed<false>, dim3(sb), dim3(lbg::kBlock), 0, st, a, static_cast<const int32_t*>(dslots), cnt, e->L);
+    HIP_TRY(hipGetLastError());
+    for (int32_t s : e->pending) e->state[static_cast<size_t>(s)] = 2;
+    e->pending.clear();
+  }
+  for (int32_t k = 0; k < levels; ++k, ++e->L) {
+    if (e->narrow)
+      hipLaunchKernelGGL((lbg::k_expand_balanced<true, true, true>), dim3(GR.multi[1]), dim3(lbg::kBlock), 0, st, a, e->L);
+    else
+      hipLaunchKernelGGL((lbg::k_expand_balanced<true, false, true>), dim3(GR.multi[0]), dim3(lbg::kBlock), 0, st, a, e->L);
+    HIP_TRY(hipGetLastError());
+  }
+  int rc = engine_sync_state(e);
+  if (rc) return rc;
+  // a running query is finished once no worklist from level L on holds it
+  e->done.clear();
+  int cnt = 0;
+  for (int32_t s = 0; s < e->max_q; ++s)
+    if (e->state[static_cast<size_t>(s)] == 2 && e->host_qlast[s] < e->L) {
+      e->done.push_back(s);
+      e->host_slots[cnt++] = s;
+    }
+  if (cnt) {
+    int32_t* dslots = reinterpret_cast<int32_t*>(e->ws + e->lay.slots);
+    HIP_TRY(hipMemcpyAsync(dslots, e->host_slots, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(lbg::k_engine_finish, dim3(std::min(cnt, 4096)), dim3(lbg::kBlock), 0, st, a,
+                       static_cast<const int32_t*>(dslots), cnt);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t s : e->done) e->state[static_cast<size_t>(s)] = 3;
+  }
+  ++e->steps;
+  if (finished) *finished = cnt;
+  return LBG_OK;
+}
+
+int32_t lbg_engine_finished(const lbg_engine* e, int32_t* slots, int32_t max_slots) {
+  if (!e || !slots) return 0;
+  const int32_t k = std::min<int32_t>(max_slots, static_cast<int32_t>(e->done.size()));
+  for (int32_t i = 0; i < k; ++i) slots[i] = e->done[static_cast<size_t>(i)];
+  return k;
+}
+
+int lbg_engine_release(lbg_engine* e, int32_t slot) {
+  if (!e || slot < 0 || slot >= e->max_q) return fail(LBG_EINVAL, "bad slot");
+  if (e->state[static_cast<size_t>(slot)] != 3) return fail(LBG_EINVAL, "slot %d has not finished", slot);
+  e->state[static_cast<size_t>(slot)] = 0;
+  return LBG_OK;
+}
+
+int lbg_engine_info(const lbg_engine* e, lbg_stats* stats, int32_t* running, uint32_t* level) {
+  if (!e) return fail(LBG_EINVAL, "null engine");
+  if (running) {
+    int32_t r = 0;
+    for (uint8_t s : e->state) r += (s == 1 || s == 2) ? 1 : 0;
+    *running = r;
+  }
+  if (level) *level = e->L;
+  if (stats) {
+    stats->levels = static_cast<int32_t>(e->host_ctl->levels);
+    stats->reserved = 0;
+    stats->frontier_entries = static_cast<int64_t>(e->host_ctl->frontier_entries);
+    stats->edges_scanned = static_cast<int64_t>(e->host_ctl->edges_scanned);
+    stats->updates = xsum(e->host_ctl, 0);
+    stats->atomics = xsum(e->host_ctl, 1);
+  }
+  return LBG_OK;
+}
+
+void lbg_engine_destroy(lbg_engine* e) {
+  if (!e) return;
+  if (e->st) (void)hipStreamSynchronize(e->st);
+  if (e->host_qlast) (void)hipHostFree(e->host_qlast);
+  if (e->host_slots) (void)hipHostFree(e->host_slots);
+  if (e->host_ctl) (void)hipHostFree(e->host_ctl);
+  delete e;
+}
+
+}  // extern "C"
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -427,13 +867,28 @@ const char* lbg_last_error(void) { return g_err; }
 void lbg_profile_enable(int32_t enable, int32_t reset) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = enable != 0;
-  if (reset) g_prof[0] = g_prof[1] = lbg_profile{};
+  if (reset) g_prof[0] = g_prof[1] = g_prof[2] = lbg_profile{};
 }
 
-void lbg_profile_read(int32_t is_sssp, lbg_profile* out) {
-  if (!out) return;
+void lbg_profile_read(int32_t which, lbg_profile* out) {
+  if (!out || which < 0 || which > 2) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  *out = g_prof[is_sssp ? 1 : 0];
+  *out = g_prof[which];
+}
+
+size_t lbg_batch_workspace_bytes(int32_t num_queries, int64_t total_rows, int64_t total_arcs) {
+  if (num_queries <= 0 || total_rows <= 0 || total_rows > INT32_MAX || total_arcs < 0 ||
+      total_arcs > UINT32_MAX)
+    return 0;
+  return batch_layout(num_queries, total_rows, total_arcs).total;
+}
+
+int lbg_batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, const lbg_query* queries, int32_t num_queries, uint32_t* out,
+                    int64_t total_rows, int64_t total_arcs, void* workspace, size_t workspace_bytes,
+                    lbg_stats* stats, void* stream) {
+  return batch_solve(offsets, cols, weights, n, m, queries, num_queries, out, total_rows,
+                     total_arcs, workspace, workspace_bytes, stats, static_cast<hipStream_t>(stream));
 }
 
 int32_t lbg_tile_edges(void) { return static_cast<int32_t>(lbg::kMinTile); }

@@ -17,12 +17,23 @@ constexpr int kWQ = 256;                 // per-wave LDS push-queue entries (bal
 // Balanced kernel: a tile is the run of consecutive edges one wavefront
 // expands at a time, 64 lanes x kItems edges.  BFS carries 16 items per lane,
 // SSSP (more state per arc) 8.
-template <bool kSssp>
+template <bool kSssp, bool kMulti = false>
 struct TileCfg {
-  static constexpr int kItems = kSssp ? 8 : 16;
+  static constexpr int kItems = kMulti ? 4 : (kSssp ? 8 : 16);
   static constexpr uint32_t kEdges = 64u * kItems;
 };
-constexpr uint32_t kMinTile = TileCfg<true>::kEdges;  // sizes the tile-mark arrays
+constexpr uint32_t kMinTile = TileCfg<true>::kEdges;          // sizes single-query tile marks
+constexpr uint32_t kMultiTile = TileCfg<true, true>::kEdges;  // sizes batched tile marks
+
+// Batched solves: one row of node state per query.  row(q, v) = v + delta.
+struct QInfo {
+  int32_t delta;      // row_start - lo
+  int32_t kind;       // 0 = BFS (unit weights, int32 levels out), 1 = SSSP
+  int32_t row_start;  // first element of the query's result row
+  int32_t row_len;    // hi - lo
+  int32_t src;        // global source node
+  int32_t pad[3];
+};
 constexpr int kXcds = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
 
 // Control block at the start of the workspace.  ctr[] are the worklist tail
@@ -59,6 +70,8 @@ struct Frontier {
   uint32_t* eprefix;
   int32_t* estart;
   int32_t* tile_node;
+  int32_t* qid;  // batched solves: the query an entry belongs to
+  uint32_t level;  // index of the level this worklist feeds (set per launch)
 };
 
 struct KArgs {
@@ -81,6 +94,10 @@ struct KArgs {
   uint32_t tile_cap;     // entries per tile_node array
   uint32_t edge_cap;     // entries per edge worklist
   uint32_t count_stats;
+  const QInfo* qtab;     // batched solves
+  uint32_t num_queries;
+  uint32_t rows;         // batched solves: total elements of node state
+  uint32_t* qlast;       // engine: per query, the last level that holds one of its entries
 };
 
 // Ctl::error bits.  None can trip for a well-formed CSR; they turn what
@@ -273,16 +290,21 @@ struct WaveQueue {
 // into one reservation, so the tail sees about one atomic per workgroup
 // rather than one per wavefront (same-address atomics serialise at ~12 ns).
 
-// Writes worklist entry i (node v, first edge p of the level's edge space,
-// first arc s, out-degree d) and marks the tiles whose first edge it holds.
-template <bool kWithNode, uint32_t kTileE, bool kNarrow>
+// Writes worklist entry i (node v of query q, first edge p of the level's
+// edge space, first arc s, out-degree d) and marks the tiles whose first edge
+// it holds.  kPay: 0 = no node id stored (BFS), 1 = node, 2 = node + query.
+template <int kPay, uint32_t kTileE, bool kNarrow>
 __device__ __forceinline__ void write_entry(const KArgs& a, const Frontier& out, uint32_t i,
-                                            uint32_t p, int32_t v, int32_t s, int32_t d) {
+                                            uint32_t p, int32_t v, int32_t q, int32_t s, int32_t d) {
   if (i >= a.node_cap) {
     atomicOr(&a.ctl->error, kErrNodeCap);
     return;
   }
-  if (kWithNode) *at<kNarrow>(out.node, i) = v;
+  if (kPay >= 1) *at<kNarrow>(out.node, i) = v;
+  if (kPay == 2) {
+    *at<kNarrow>(out.qid, i) = q;
+    if (a.qlast) a.qlast[q] = out.level;  // same value from every writer: no atomic needed
+  }
   *at<kNarrow>(out.eprefix, i) = p;
   *at<kNarrow>(out.estart, i) = s;
   const uint32_t end = p + static_cast<uint32_t>(d);
@@ -293,10 +315,10 @@ __device__ __forceinline__ void write_entry(const KArgs& a, const Frontier& out,
 }
 
 // Wave-direct append of the lanes with `act` set (convergent); used when a
-// wave queue cannot take a whole push.
-template <bool kWithNode, uint32_t kTileE, bool kNarrow>
-__device__ __forceinline__ void wave_append(const KArgs& a, bool act, int32_t v, const Frontier& out,
-                                            int ctr_idx) {
+// wave queue cannot take a whole push, and to seed batched worklists.
+template <int kPay, uint32_t kTileE, bool kNarrow>
+__device__ __forceinline__ void wave_append(const KArgs& a, bool act, int32_t v, int32_t q,
+                                            const Frontier& out, int ctr_idx) {
   int32_t s = 0, d = 0;
   if (act) {
     s = *at<kNarrow>(a.offsets, v);
@@ -314,37 +336,42 @@ __device__ __forceinline__ void wave_append(const KArgs& a, bool act, int32_t v,
                      (static_cast<unsigned long long>(__popcll(mask)) << 32) | tot);
   base = bcast64(base, 0);
   if (ok)
-    write_entry<kWithNode, kTileE, kNarrow>(a, out, static_cast<uint32_t>(base >> 32) + lane_rank(mask),
-                                            static_cast<uint32_t>(base) + inc - dd, v, s, d);
+    write_entry<kPay, kTileE, kNarrow>(a, out, static_cast<uint32_t>(base >> 32) + lane_rank(mask),
+                                       static_cast<uint32_t>(base) + inc - dd, v, q, s, d);
 }
 
-// Queue v if `want` (convergent per wave).  `count` is wave-uniform.
-template <bool kWithNode, uint32_t kTileE, bool kNarrow>
-__device__ __forceinline__ void wq_push(const KArgs& a, int32_t* qv, uint32_t& count, bool want,
-                                        int32_t v, const Frontier& out, int ctr_idx) {
+// Queue (v, q) if `want` (convergent per wave).  `count` is wave-uniform.
+template <int kPay, uint32_t kTileE, bool kNarrow>
+__device__ __forceinline__ void wq_push(const KArgs& a, int32_t* qv, int32_t* qq, uint32_t& count,
+                                        bool want, int32_t v, int32_t q, const Frontier& out,
+                                        int ctr_idx) {
   const uint64_t mask = __ballot(want);
   if (mask == 0) return;
   const uint32_t k = count + lane_rank(mask);
   const bool fits = want && k < static_cast<uint32_t>(kWQ);
-  if (fits) qv[k] = v;
+  if (fits) {
+    qv[k] = v;
+    if (kPay == 2) qq[k] = q;
+  }
   const uint32_t c = static_cast<uint32_t>(__popcll(mask));
   count = min(count + c, static_cast<uint32_t>(kWQ));
   const bool over = want && !fits;
-  if (__ballot(over)) wave_append<kWithNode, kTileE, kNarrow>(a, over, v, out, ctr_idx);
+  if (__ballot(over)) wave_append<kPay, kTileE, kNarrow>(a, over, v, q, out, ctr_idx);
   __builtin_amdgcn_wave_barrier();
 }
 
 // A wave queue's flush, split so a workgroup can merge the reservations of
 // its four queues: prepare() reads degrees and scans within the wave,
 // write() stores the entries once the base of the reservation is known.
-template <bool kWithNode, uint32_t kTileE, bool kNarrow>
+template <int kPay, uint32_t kTileE, bool kNarrow>
 struct WaveFlush {
   static constexpr int R = kWQ / 64;
-  int32_t vs[R], ss[R], ds[R];
+  int32_t vs[R], ss[R], ds[R], qs[kPay == 2 ? R : 1];
   uint32_t pn[R], pe[R];
   uint32_t tot_n, tot_e;
 
-  __device__ __forceinline__ void prepare(const KArgs& a, const int32_t* qv, uint32_t count) {
+  __device__ __forceinline__ void prepare(const KArgs& a, const int32_t* qv, const int32_t* qq,
+                                          uint32_t count) {
     const uint32_t lane = lane_id();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -352,7 +379,11 @@ struct WaveFlush {
       vs[r] = 0;
       ss[r] = 0;
       ds[r] = 0;
-      if (k < count) vs[r] = qv[k];
+      if (kPay == 2) qs[r] = 0;
+      if (k < count) {
+        vs[r] = qv[k];
+        if (kPay == 2) qs[r] = qq[k];
+      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -382,13 +413,14 @@ struct WaveFlush {
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (ds[r] > 0)
-        write_entry<kWithNode, kTileE, kNarrow>(a, out, nb + pn[r], eb + pe[r], vs[r], ss[r], ds[r]);
+        write_entry<kPay, kTileE, kNarrow>(a, out, nb + pn[r], eb + pe[r], vs[r],
+                                           kPay == 2 ? qs[kPay == 2 ? r : 0] : 0, ss[r], ds[r]);
   }
 
   // Standalone flush by one wavefront.
-  __device__ __forceinline__ void flush(const KArgs& a, const int32_t* qv, uint32_t count,
-                                        const Frontier& out, int ctr_idx) {
-    prepare(a, qv, count);
+  __device__ __forceinline__ void flush(const KArgs& a, const int32_t* qv, const int32_t* qq,
+                                        uint32_t count, const Frontier& out, int ctr_idx) {
+    prepare(a, qv, qq, count);
     if (tot_n == 0) return;
     unsigned long long base = 0;
     if (lane_id() == 0)

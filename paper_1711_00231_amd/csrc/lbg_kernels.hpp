@@ -23,7 +23,11 @@
 //    relaxes with a single 64-bit atomicMin: the returned old value says both
 //    whether the arc improved the node and whether the node is already queued
 //    for this iteration (the worklist condensing concern of Section II-B is
-//    handled at push time, with no second atomic).
+//    handled at push time, with no second atomic).  The per-arc filter reads
+//    the caller's 4-byte output array instead of the 8-byte state (half the
+//    random-read footprint); winners refresh it with plain stores, so it may
+//    lag the state but never undercuts it, and the epilogue rewrites it from
+//    the state.  A frontier node's own distance is always read from the state.
 // Plain reads may be stale inside a launch; values only move one way (bits
 // set, distances decrease), so a stale read can only cost an extra atomic,
 // never a missed update.
@@ -112,11 +116,12 @@ __device__ __forceinline__ bool relax(const KArgs& a, uint32_t L, int32_t v, uin
     ++*upd;
   } else {
     const uint32_t alt = du + w;
-    if (alt >= static_cast<uint32_t>(a.dstate[v] >> 32)) return false;
+    if (alt >= a.dist[v]) return false;
     const unsigned long long mine = (static_cast<unsigned long long>(alt) << 32) | (L + 1);
     ++*atom;
     const unsigned long long old = atomicMin(&a.dstate[v], mine);
     if (alt >= static_cast<uint32_t>(old >> 32)) return false;
+    a.dist[v] = alt;  // filter copy; may lag the state, never undercuts it
     ++*upd;
     if (static_cast<uint32_t>(old) == L + 1) return false;  // already queued this iteration
   }
@@ -137,6 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
     if (kSssp) {
       a.dstate[v] = (v == static_cast<uint32_t>(src)) ? 0ull
                                                       : (static_cast<unsigned long long>(kSsspInf) << 32);
+      a.dist[v] = (v == static_cast<uint32_t>(src)) ? 0u : kSsspInf;
     } else {
       a.levels[v] = (v == static_cast<uint32_t>(src)) ? 0 : static_cast<int32_t>(kBfsInf);
     }
@@ -212,14 +218,19 @@ __global__ __launch_bounds__(kBlock) void k_sssp_finish(KArgs a, uint32_t L) {
 // lane's kItems loads (or atomics) before consuming any, the next tile's
 // start entry is fetched one tile ahead, and discoveries go to per-wave LDS
 // queues whose degree reads happen in bulk at flush time.
-template <bool kSssp>
+template <bool kSssp, bool kMulti>
 struct WaveLds {
-  static constexpr uint32_t T = TileCfg<kSssp>::kEdges;
+  static constexpr uint32_t T = TileCfg<kSssp, kMulti>::kEdges;
   uint32_t base[T];
   uint32_t du[kSssp ? T : 1];
+  int32_t delta[kMulti ? T : 1];
+  int32_t lo[kMulti ? T : 1];        // first node of the query's instance
+  uint32_t lenkind[kMulti ? T : 1];  // instance size | (kind << 31)
+  int32_t qid[kMulti ? T : 1];
   uint32_t flag[T / 32];
   uint32_t wpre[T / 32];
   int32_t qv[kWQ];
+  int32_t qq[kMulti ? kWQ : 1];
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -227,11 +238,15 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <bool kSssp, bool kNarrow>
+// kMulti: batched solves (always the SSSP relaxation; BFS queries use unit
+// weights).  Entry (q, u) relaxes arc u -> v into row(q, v) = v + delta(q).
+template <bool kSssp, bool kNarrow, bool kMulti = false>
 __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
-  constexpr int kItems = TileCfg<kSssp>::kItems;
-  constexpr uint32_t T = TileCfg<kSssp>::kEdges;
-  __shared__ WaveLds<kSssp> lds[kWaves];
+  static_assert(!kMulti || kSssp, "batched solves use the SSSP relaxation");
+  constexpr int kItems = TileCfg<kSssp, kMulti>::kItems;
+  constexpr uint32_t T = TileCfg<kSssp, kMulti>::kEdges;
+  constexpr int kPay = kMulti ? 2 : (kSssp ? 1 : 0);
+  __shared__ WaveLds<kSssp, kMulti> lds[kWaves];
   __shared__ uint32_t merge[2 * kWaves];
   __shared__ unsigned long long merge_base;
 
@@ -239,21 +254,25 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
   const uint32_t Ef = static_cast<uint32_t>(c);
   const uint32_t nf = static_cast<uint32_t>(c >> 32);
   if (Ef == 0) return;
-  if (nf > a.node_cap || Ef > a.m) {
+  if (nf > a.node_cap ||
+      Ef > (kMulti ? static_cast<unsigned long long>(a.tile_cap) * T : static_cast<unsigned long long>(a.m))) {
     if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrNodeCap);
     return;
   }
   const Frontier cur = a.fr[L & 1];
-  const Frontier nxt = a.fr[(L + 1) & 1];
+  Frontier nxt = a.fr[(L + 1) & 1];
+  nxt.level = L + 1;
   const int nctr = (L + 1) % 3;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wid = threadIdx.x >> 6;
-  WaveLds<kSssp>& w = lds[wid];
+  WaveLds<kSssp, kMulti>& w = lds[wid];
   uint32_t* fx = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
   const uint32_t* seen_cur = a.seen[L & 1];
   uint32_t* seen_nxt = a.seen[(L + 1) & 1];
-  // SSSP compares against the distance half of the packed state only
+  // A frontier node's own distance comes from the distance half of the
+  // packed state (authoritative); the per-arc filter reads the output array.
   const uint32_t* dist_hi = reinterpret_cast<const uint32_t*>(a.dstate) + 1;
+  const uint32_t state_len = kMulti ? a.rows : a.n;
   uint32_t upd = 0, atom = 0, qcount = 0;
   if (!kSssp) refresh_seen(a, L);
 
@@ -275,6 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
     // Stage the entries overlapping [t0, t1): a contiguous run starting at i0
     // of at most T entries (each holds >= 1 edge).  An entry's reads are
     // issued together.
+    bool bad = false;  // malformed input (see lbg_validate_csr): flagged, arc skipped
     for (uint32_t j = lane; j < T; j += 64) {
       const uint32_t i = i0 + j;
       bool valid = false;
@@ -282,10 +302,24 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
         const uint32_t p = *at<kNarrow>(cur.eprefix, i);
         const uint32_t st = static_cast<uint32_t>(*at<kNarrow>(cur.estart, i));
         const int32_t node = kSssp ? *at<kNarrow>(cur.node, i) : 0;
+        const int32_t q = kMulti ? *at<kNarrow>(cur.qid, i) : 0;
         if (p < t1) {
           valid = true;
           w.base[j] = st + t0 - p;  // arc of slot s is base + s (mod 2^32)
-          if (kSssp) w.du[j] = *at<kNarrow>(dist_hi, 2u * static_cast<uint32_t>(node));
+          int32_t delta = 0;
+          if (kMulti) {
+            const QInfo qi = a.qtab[q];
+            delta = qi.delta;
+            w.delta[j] = qi.delta;
+            w.lo[j] = qi.row_start - qi.delta;
+            w.lenkind[j] = static_cast<uint32_t>(qi.row_len) | (qi.kind ? 0x80000000u : 0u);
+            w.qid[j] = q;
+          }
+          if (kSssp) {
+            const uint32_t row = static_cast<uint32_t>(node + delta);
+            if (row < state_len) w.du[j] = *at<kNarrow>(dist_hi, 2u * row);
+            else { w.du[j] = kSsspInf; bad = true; }
+          }
           const uint32_t s = (p > t0 ? p : t0) - t0;
           atomicOr(&w.flag[s >> 5], 1u << (s & 31));
         }
@@ -301,16 +335,23 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
     wave_sync();
 
     // Phase A: the arcs of this lane's kItems slots.
-    bool bad = false;  // malformed CSR (see lbg_validate_csr): flagged, arc skipped
     int32_t vv[kItems];
     uint32_t ww[kItems];
     uint32_t du[kItems];
+    int32_t dl[kMulti ? kItems : 1];
+    int32_t qd[kMulti ? kItems : 1];
+    bool inside[kMulti ? kItems : 1];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t s = r * 64 + lane;
       vv[r] = -1;
       ww[r] = 0;
       du[r] = 0;
+      if (kMulti) {
+        dl[kMulti ? r : 0] = 0;
+        qd[kMulti ? r : 0] = 0;
+        inside[kMulti ? r : 0] = true;
+      }
       if (t0 + s < t1) {
         const uint32_t k = s >> 5;
         const uint32_t msk = static_cast<uint32_t>((2ull << (s & 31)) - 1ull);
@@ -319,25 +360,37 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
         if (e < a.m) {
           vv[r] = *at<kNarrow>(a.cols, e);
           if (kSssp) {
-            ww[r] = *at<kNarrow>(a.weights, e);
             du[r] = w.du[slot];
+            if (kMulti) {
+              dl[kMulti ? r : 0] = w.delta[slot];
+              qd[kMulti ? r : 0] = w.qid[slot];
+              const uint32_t lk = w.lenkind[slot];
+              inside[kMulti ? r : 0] =
+                  static_cast<uint32_t>(vv[r] - w.lo[slot]) < (lk & 0x7fffffffu);
+              ww[r] = (lk >> 31) ? *at<kNarrow>(a.weights, e) : 1u;
+            } else {
+              ww[r] = *at<kNarrow>(a.weights, e);
+            }
           }
         } else {
           bad = true;
         }
       }
     }
+    uint32_t row[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-      if (vv[r] >= 0 && static_cast<uint32_t>(vv[r]) >= a.n) {  // malformed cols
-        bad = true;
+      row[r] = static_cast<uint32_t>(vv[r] + (kMulti ? dl[kMulti ? r : 0] : 0));
+      if (vv[r] >= 0 && (static_cast<uint32_t>(vv[r]) >= a.n || row[r] >= state_len ||
+                         (kMulti && !inside[kMulti ? r : 0]))) {
+        bad = true;  // malformed cols, or an arc leaving its query's instance
         vv[r] = -1;
       }
     }
     bool push[kItems];
     if (!kSssp) {
-      // Phase B: visited words; phase C: this XCD's advisory filter; phase D:
-      // one atomic per surviving candidate.
+      // Phase B: frozen visited snapshot; phase C: this XCD's advisory
+      // filter; phase D: one atomic per surviving candidate.
       uint32_t x[kItems];
 #pragma unroll
       for (int r = 0; r < kItems; ++r) x[r] = vv[r] >= 0 ? *at<kNarrow>(seen_cur, static_cast<uint32_t>(vv[r]) >> 5) : ~0u;
@@ -349,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
         const uint32_t bit = 1u << (vv[r] & 31);
         const bool cand = vv[r] >= 0 && !(x[r] & bit);
         if (cand) {
-          *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) = x[r] | bit;  // plain store: a lost bit costs one more atomic
+          *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) = x[r] | bit;  // a lost bit costs one more atomic
           ++atom;
           x[r] = atomicOr(at<kNarrow>(a.visited, static_cast<uint32_t>(vv[r]) >> 5), bit);
         } else {
@@ -367,13 +420,13 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
         }
       }
     } else {
-      // Phase B: current distances; phase C: one 64-bit atomicMin per
+      // Phase B: filter distances; phase C: one 64-bit atomicMin per
       // improving arc, returning both the old distance and whether the node
       // is already queued for this iteration.
       uint32_t cd[kItems];
 #pragma unroll
       for (int r = 0; r < kItems; ++r)
-        cd[r] = vv[r] >= 0 ? *at<kNarrow>(dist_hi, 2u * static_cast<uint32_t>(vv[r])) : 0u;
+        cd[r] = vv[r] >= 0 ? *at<kNarrow>(static_cast<const uint32_t*>(a.dist), row[r]) : 0u;
       unsigned long long old[kItems];
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
@@ -381,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
         old[r] = 0ull;
         if (vv[r] >= 0 && alt < cd[r]) {
           ++atom;
-          old[r] = atomicMin(at<kNarrow>(a.dstate, vv[r]),
+          old[r] = atomicMin(at<kNarrow>(a.dstate, row[r]),
                              (static_cast<unsigned long long>(alt) << 32) | (L + 1));
         }
       }
@@ -389,24 +442,27 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
       for (int r = 0; r < kItems; ++r) {
         const uint32_t alt = du[r] + ww[r];
         const bool better = vv[r] >= 0 && alt < static_cast<uint32_t>(old[r] >> 32);
+        if (better) *at<kNarrow>(a.dist, row[r]) = alt;  // filter copy (see top of file)
         upd += better ? 1u : 0u;
         push[r] = better && static_cast<uint32_t>(old[r]) != L + 1;
       }
     }
     if (__any(bad) && lane == 0) atomicOr(&a.ctl->error, kErrBadArc);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) wq_push<kSssp, T, kNarrow>(a, w.qv, qcount, push[r], vv[r], nxt, nctr);
+    for (int r = 0; r < kItems; ++r)
+      wq_push<kPay, T, kNarrow>(a, w.qv, w.qq, qcount, push[r], vv[r], kMulti ? qd[kMulti ? r : 0] : 0,
+                                nxt, nctr);
     if (qcount >= kWQ / 2) {
-      WaveFlush<kSssp, T, kNarrow> f;
-      f.flush(a, w.qv, qcount, nxt, nctr);
+      WaveFlush<kPay, T, kNarrow> f;
+      f.flush(a, w.qv, w.qq, qcount, nxt, nctr);
       qcount = 0;
     }
     wave_sync();
   }
 
   // Final flush: one reservation for the whole workgroup.
-  WaveFlush<kSssp, T, kNarrow> f;
-  f.prepare(a, w.qv, qcount);
+  WaveFlush<kPay, T, kNarrow> f;
+  f.prepare(a, w.qv, w.qq, qcount);
   if (lane == 0) {
     merge[wid] = f.tot_n;
     merge[kWaves + wid] = f.tot_e;
@@ -533,6 +589,112 @@ __global__ __launch_bounds__(kBlock) void k_expand_edge(KArgs a, uint32_t L) {
   }
   flush();
   add_stats(a, upd, atom);
+}
+
+// ------------------------------------------------------------- batched --
+// Batched solves: every query owns a row of node state; the queries' rows
+// (and nothing between them) start at infinity and the control block is
+// cleared.
+__global__ __launch_bounds__(kBlock) void k_batch_fill(KArgs a) {
+  const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+  for (uint32_t q = blockIdx.x; q < a.num_queries; q += gridDim.x) {
+    const QInfo qi = a.qtab[q];
+    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
+      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
+      a.dstate[idx] = static_cast<unsigned long long>(kSsspInf) << 32;
+      a.dist[idx] = kSsspInf;
+    }
+  }
+  if (gid == 0) {
+    a.ctl->ctr[0] = a.ctl->ctr[1] = a.ctl->ctr[2] = 0ull;
+    a.ctl->error = 0u;
+    a.ctl->levels = 0u;
+    a.ctl->frontier_entries = 0ull;
+    a.ctl->edges_scanned = 0ull;
+  }
+  if (gid < kXcds * 16) a.ctl->xstat[gid / 16][gid % 16] = 0ull;
+}
+
+// Each query's source gets distance 0 and (query, source) enters worklist 0.
+template <bool kNarrow>
+__global__ __launch_bounds__(kBlock) void k_batch_seed(KArgs a) {
+  const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+  const bool act = q < a.num_queries;
+  int32_t v = 0;
+  if (act) {
+    const QInfo qi = a.qtab[q];
+    v = qi.src;
+    const uint32_t row = static_cast<uint32_t>(v + qi.delta);
+    a.dstate[row] = 0ull;
+    a.dist[row] = 0u;
+  }
+  Frontier f0 = a.fr[0];
+  f0.level = 0;
+  wave_append<2, kMultiTile, kNarrow>(a, act, v, static_cast<int32_t>(q), f0, 0);
+}
+
+// ------------------------------------------------------------------ engine --
+// Continuous batching: queries join a running batch between levels.  Rows of
+// the listed slots start at infinity ...
+__global__ __launch_bounds__(kBlock) void k_engine_fill(KArgs a, const int32_t* slots, int count) {
+  for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    const QInfo qi = a.qtab[slots[k]];
+    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
+      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
+      a.dstate[idx] = static_cast<unsigned long long>(kSsspInf) << 32;
+      a.dist[idx] = kSsspInf;
+    }
+  }
+}
+
+// ... then each source gets distance 0 and joins worklist L, the next one to
+// be expanded (appending to it exactly like a push of the previous level).
+template <bool kNarrow>
+__global__ __launch_bounds__(kBlock) void k_engine_seed(KArgs a, const int32_t* slots, int count,
+                                                        uint32_t L) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const bool act = k < count;
+  int32_t v = 0, q = 0;
+  if (act) {
+    q = slots[k];
+    const QInfo qi = a.qtab[q];
+    v = qi.src;
+    const uint32_t row = static_cast<uint32_t>(v + qi.delta);
+    a.dstate[row] = 0ull;
+    a.dist[row] = 0u;
+    a.qlast[q] = L;  // even a source without out-arcs is live until level L ends
+  }
+  Frontier f = a.fr[L & 1];
+  f.level = L;
+  wave_append<2, kMultiTile, kNarrow>(a, act, v, q, f, static_cast<int>(L % 3));
+}
+
+// Rows of finished slots are written out (as k_batch_finish).
+__global__ __launch_bounds__(kBlock) void k_engine_finish(KArgs a, const int32_t* slots, int count) {
+  for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    const QInfo qi = a.qtab[slots[k]];
+    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
+      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
+      const uint32_t d = static_cast<uint32_t>(a.dstate[idx] >> 32);
+      a.dist[idx] = (qi.kind || d != kSsspInf) ? d : kBfsInf;
+    }
+  }
+}
+
+// Once worklist L is empty, each row is written out: SSSP rows as distances,
+// BFS rows as int32 levels (INT32_MAX for unreached).
+__global__ __launch_bounds__(kBlock) void k_batch_finish(KArgs a, uint32_t L) {
+  const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  if (static_cast<uint32_t>(c) != 0u) return;
+  for (uint32_t q = blockIdx.x; q < a.num_queries; q += gridDim.x) {
+    const QInfo qi = a.qtab[q];
+    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
+      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
+      const uint32_t d = static_cast<uint32_t>(a.dstate[idx] >> 32);
+      a.dist[idx] = (qi.kind || d != kSsspInf) ? d : kBfsInf;
+    }
+  }
 }
 
 // ------------------------------------------------------- CSR validation --

@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbg.so")
 
-OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 AUTO, NODE, EDGE, BALANCED = 0, 1, 2, 3
 STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED}
 BFS_INF = 2**31 - 1
@@ -35,6 +35,14 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+KIND_BFS, KIND_SSSP = 0, 1
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("lo", ctypes.c_int32), ("hi", ctypes.c_int32),
+                ("kind", ctypes.c_int32), ("out_off", ctypes.c_int64)]
 
 
 class Profile(ctypes.Structure):
@@ -69,6 +77,29 @@ def _load():
     lib.lbg_profile_enable.argtypes = [i32, i32]
     lib.lbg_profile_read.restype = None
     lib.lbg_profile_read.argtypes = [i32, ctypes.POINTER(Profile)]
+    lib.lbg_batch_workspace_bytes.restype = sz
+    lib.lbg_batch_workspace_bytes.argtypes = [i32, i64, i64]
+    lib.lbg_batch_solve.restype = ctypes.c_int
+    lib.lbg_batch_solve.argtypes = [vp, vp, vp, i32, i64, ctypes.POINTER(Query), i32, vp, i64, i64,
+                                    vp, sz, ctypes.POINTER(Stats), vp]
+    lib.lbg_engine_workspace_bytes.restype = sz
+    lib.lbg_engine_workspace_bytes.argtypes = [i32, i64, i64]
+    lib.lbg_engine_create.restype = ctypes.c_int
+    lib.lbg_engine_create.argtypes = [vp, vp, vp, i32, i64, i32, i64, i64, vp, vp, sz, vp,
+                                      ctypes.POINTER(vp)]
+    lib.lbg_engine_submit.restype = ctypes.c_int
+    lib.lbg_engine_submit.argtypes = [vp, ctypes.POINTER(Query), ctypes.POINTER(i32)]
+    lib.lbg_engine_step.restype = ctypes.c_int
+    lib.lbg_engine_step.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.lbg_engine_finished.restype = i32
+    lib.lbg_engine_finished.argtypes = [vp, ctypes.POINTER(i32), i32]
+    lib.lbg_engine_release.restype = ctypes.c_int
+    lib.lbg_engine_release.argtypes = [vp, i32]
+    lib.lbg_engine_info.restype = ctypes.c_int
+    lib.lbg_engine_info.argtypes = [vp, ctypes.POINTER(Stats), ctypes.POINTER(i32),
+                                    ctypes.POINTER(ctypes.c_uint32)]
+    lib.lbg_engine_destroy.restype = None
+    lib.lbg_engine_destroy.argtypes = [vp]
     lib.lbg_tile_edges.restype = i32
     lib.lbg_tile_edges.argtypes = []
     lib.lbg_grid_blocks.restype = i32
@@ -114,6 +145,7 @@ class DeviceGraph:
     cols: torch.Tensor
     weights: torch.Tensor | None
     coo_src: torch.Tensor | None = None
+    host_offsets: object = None  # numpy copy, used to size batched solves
 
     @property
     def n(self) -> int:
@@ -132,7 +164,7 @@ class DeviceGraph:
         w = None
         if weights is not None:
             w = torch.from_numpy(np.ascontiguousarray(weights, dtype=np.uint32).view(np.int32)).to(device)
-        g = cls(off, c, w)
+        g = cls(off, c, w, None, np.ascontiguousarray(offsets, dtype=np.int64))
         if with_coo:
             g.ensure_coo()
         return g
@@ -207,6 +239,119 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
     return (out, st.as_dict()) if stats else out
 
 
+def batch_queries(queries):
+    """Query array from (src, lo, hi, kind[, out_off]) tuples; missing row
+    offsets are assigned back to back.  Returns (Query array, total_rows)."""
+    arr = (Query * len(queries))()
+    off = 0
+    for i, q in enumerate(queries):
+        src, lo, hi, kind = (int(x) for x in q[:4])
+        o = int(q[4]) if len(q) > 4 else off
+        arr[i].src, arr[i].lo, arr[i].hi, arr[i].kind, arr[i].out_off = src, lo, hi, kind, o
+        off = max(off, o + hi - lo)
+    return arr, off
+
+
+def batch_workspace_bytes(num_queries: int, total_rows: int, total_arcs: int) -> int:
+    return int(lib.lbg_batch_workspace_bytes(num_queries, total_rows, total_arcs))
+
+
+def batch_solve(g: DeviceGraph, queries, out: torch.Tensor | None = None, total_arcs=None,
+                workspace: Workspace | None = None, stats: bool = False, stream=None):
+    """Solve many BFS (kind 0) / SSSP (kind 1) queries over a packed graph in
+    one level-synchronous batch (see lbg_batch_solve).  ``queries``: sequence
+    of (src, lo, hi, kind[, out_off]) with global node ids.  Returns the int32
+    result tensor (BFS rows: levels; SSSP rows: uint32 bit patterns) or
+    (tensor, stats)."""
+    if g.weights is None:
+        raise ValueError("batched solves need weights (BFS queries ignore them)")
+    qarr, rows = batch_queries(queries)
+    if total_arcs is None:
+        if g.host_offsets is None:
+            raise ValueError("total_arcs is required when the graph has no host offsets")
+        ho = g.host_offsets
+        total_arcs = int(sum(int(ho[q.hi]) - int(ho[q.lo]) for q in qarr))
+    if out is None:
+        out = torch.empty(max(rows, 1), dtype=torch.int32, device=g.offsets.device)
+    need = batch_workspace_bytes(len(qarr), out.numel(), total_arcs)
+    if need == 0:
+        raise LbgError(EINVAL, "invalid batch sizes")
+    ws = _ws(workspace, need, g.offsets.device)
+    st = Stats()
+    rc = lib.lbg_batch_solve(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, qarr,
+                             len(qarr), _ptr(out), out.numel(), total_arcs, _ptr(ws), ws.numel(),
+                             ctypes.byref(st) if stats else None, _stream(stream))
+    _check(rc)
+    return (out, st.as_dict()) if stats else out
+
+
+class Engine:
+    """Continuous-batching engine over one packed graph (lbg_engine_*).
+    Rows of results live in ``self.rows`` (int32 tensor of max_rows); the
+    caller assigns each query's row offset (admission is the caller's)."""
+
+    def __init__(self, g: DeviceGraph, max_queries: int, max_rows: int, max_level_arcs: int,
+                 stream=None):
+        if g.weights is None:
+            raise ValueError("the engine needs weights (BFS queries ignore them)")
+        self.g = g
+        self.max_queries = int(max_queries)
+        self.max_rows = int(max_rows)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        need = int(lib.lbg_engine_workspace_bytes(max_queries, max_rows, max_level_arcs))
+        if need == 0:
+            raise LbgError(EINVAL, "invalid engine capacities")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=g.offsets.device)
+        self.rows = torch.empty(max_rows, dtype=torch.int32, device=g.offsets.device)
+        h = ctypes.c_void_p()
+        _check(lib.lbg_engine_create(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m,
+                                     max_queries, max_rows, max_level_arcs, _ptr(self.rows),
+                                     _ptr(self.ws), need, _stream(self.stream), ctypes.byref(h)))
+        self.h = h
+        self._done = (ctypes.c_int32 * self.max_queries)()
+
+    def submit(self, src: int, lo: int, hi: int, kind: int, out_off: int) -> int:
+        q = Query(int(src), int(lo), int(hi), int(kind), int(out_off))
+        slot = ctypes.c_int32(-1)
+        rc = lib.lbg_engine_submit(self.h, ctypes.byref(q), ctypes.byref(slot))
+        if rc == EBUSY:
+            return -1
+        _check(rc)
+        return slot.value
+
+    def step(self, levels: int = 1) -> list:
+        """Run `levels` levels; returns the slots that finished."""
+        n = ctypes.c_int32(0)
+        _check(lib.lbg_engine_step(self.h, int(levels), ctypes.byref(n)))
+        k = lib.lbg_engine_finished(self.h, self._done, self.max_queries)
+        return [self._done[i] for i in range(k)]
+
+    def release(self, slot: int) -> None:
+        _check(lib.lbg_engine_release(self.h, int(slot)))
+
+    def info(self) -> dict:
+        st = Stats()
+        running = ctypes.c_int32(0)
+        level = ctypes.c_uint32(0)
+        _check(lib.lbg_engine_info(self.h, ctypes.byref(st), ctypes.byref(running),
+                                   ctypes.byref(level)))
+        d = st.as_dict()
+        d["running"] = running.value
+        d["level"] = level.value
+        return d
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            lib.lbg_engine_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def validate_csr(g: DeviceGraph, workspace: Workspace | None = None, stream=None) -> None:
     need = workspace_bytes(g.n, g.m, NODE, False)
     ws = _ws(workspace, need, g.offsets.device)
@@ -218,11 +363,12 @@ def profile_enable(enable: bool = True, reset: bool = True) -> None:
     lib.lbg_profile_enable(int(enable), int(reset))
 
 
-def profile_read(sssp: bool) -> dict:
-    """Expansion-kernel totals of BFS (sssp=False) or SSSP solves since the
-    last reset."""
+def profile_read(which) -> dict:
+    """Expansion-kernel totals since the last reset: which = "bfs", "sssp" or
+    "batch" (booleans select sssp/bfs)."""
+    idx = {"bfs": 0, "sssp": 1, "batch": 2}.get(which, None) if isinstance(which, str) else int(bool(which))
     p = Profile()
-    lib.lbg_profile_read(int(sssp), ctypes.byref(p))
+    lib.lbg_profile_read(idx, ctypes.byref(p))
     return p.as_dict()
 
 

@@ -1,0 +1,283 @@
+"""Serving loop with continuous batching on top of the lbg engine.
+
+Graphs stay resident in HBM as one packed CSR (instances with disjoint node
+ranges, plus fixed upload regions that per-request graphs are copied into).
+Requests arrive over time; the server admits a request when a query slot, a
+result row of its instance's size and (for an uploaded graph) an upload
+region are free, and the engine folds it into the running level-synchronous
+batch at the next level boundary.  Finished queries leave the batch, their
+resources return to the pools, and latency = completion - arrival is
+recorded.  Admission is first-come first-served: a request that does not fit
+blocks the ones behind it, so no request starves.
+
+The engine is injected: anything with submit/step/release/rows works, which
+is how the scheduling logic is tested without a GPU.
+"""
+from __future__ import annotations
+
+import bisect
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+KIND_BFS, KIND_SSSP = 0, 1
+
+
+class RowAllocator:
+    """First-fit allocator of contiguous result rows in [0, capacity)."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.free = [(0, self.capacity)]  # sorted (start, length)
+
+    def alloc(self, length: int):
+        for i, (s, n) in enumerate(self.free):
+            if n >= length:
+                if n == length:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (s + length, n - length)
+                return s
+        return None
+
+    def release(self, start: int, length: int) -> None:
+        i = bisect.bisect_left(self.free, (start, 0))
+        self.free.insert(i, (start, length))
+        # merge with neighbours
+        merged = []
+        for s, n in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == s:
+                merged[-1] = (merged[-1][0], merged[-1][1] + n)
+            else:
+                merged.append((s, n))
+        self.free = merged
+
+    @property
+    def in_use(self) -> int:
+        return self.capacity - sum(n for _, n in self.free)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds from the start of the run
+    kind: int               # KIND_BFS or KIND_SSSP
+    instance: str | None    # a resident instance, or None for an uploaded graph
+    src: int                # local source id within the instance
+    graph: object = None    # uploaded graph (graphgen.Graph) when instance is None
+    # filled by the server
+    admitted: float = -1.0
+    done: float = -1.0
+    slot: int = -1
+    row: int = -1
+    length: int = 0
+    region: int = -1
+    arcs: int = 0
+    result: np.ndarray | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class Instance:
+    lo: int
+    hi: int
+    arcs: int
+
+
+@dataclass
+class ServeReport:
+    completed: list = field(default_factory=list)
+    wall: float = 0.0
+    steps: int = 0
+
+    def summary(self) -> dict:
+        lat = np.array([r.latency for r in self.completed]) * 1e3
+        arcs = sum(r.arcs for r in self.completed)
+        out = {"requests": len(self.completed), "wall_s": round(self.wall, 4), "steps": self.steps}
+        if lat.size:
+            out.update({"p50_ms": round(float(np.percentile(lat, 50)), 4),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                        "mean_ms": round(float(lat.mean()), 4),
+                        "qps": round(len(self.completed) / self.wall, 2) if self.wall > 0 else None,
+                        "gteps": round(arcs / self.wall / 1e9, 4) if self.wall > 0 else None})
+        return out
+
+
+class Server:
+    """FCFS admission + continuous batching over an engine.
+
+    instances: name -> Instance (node range of a resident graph in the packed
+    CSR).  upload: optional UploadArena for per-request graphs.
+    """
+
+    def __init__(self, engine, instances: dict, upload=None, levels_per_step: int = 1,
+                 keep_results: bool = False):
+        self.engine = engine
+        self.instances = instances
+        self.upload = upload
+        self.levels_per_step = int(levels_per_step)
+        self.keep_results = keep_results
+        self.rows = RowAllocator(engine.max_rows)
+        self.inflight: dict[int, Request] = {}
+
+    # -- admission ---------------------------------------------------------
+    def _try_admit(self, r: Request, now: float) -> bool:
+        if r.instance is not None:
+            inst = self.instances[r.instance]
+            lo, hi, arcs = inst.lo, inst.hi, inst.arcs
+        else:
+            if self.upload is None:
+                raise ValueError("request carries a graph but the server has no upload arena")
+            region = self.upload.acquire()
+            if region is None:
+                return False
+            lo, hi, arcs = self.upload.load(region, r.graph)
+            r.region = region
+        row = self.rows.alloc(hi - lo)
+        if row is None:
+            if r.region >= 0:
+                self.upload.release(r.region)
+                r.region = -1
+            return False
+        slot = self.engine.submit(lo + r.src, lo, hi, r.kind, row)
+        if slot < 0:
+            self.rows.release(row, hi - lo)
+            if r.region >= 0:
+                self.upload.release(r.region)
+                r.region = -1
+            return False
+        r.slot, r.row, r.length, r.arcs, r.admitted = slot, row, hi - lo, arcs, now
+        self.inflight[slot] = r
+        return True
+
+    def _complete(self, slot: int, now: float) -> Request:
+        r = self.inflight.pop(slot)
+        r.done = now
+        if self.keep_results:
+            r.result = self.engine.rows[r.row: r.row + r.length].cpu().numpy().copy()
+        self.engine.release(slot)
+        self.rows.release(r.row, r.length)
+        if r.region >= 0:
+            self.upload.release(r.region)
+        return r
+
+    # -- loop --------------------------------------------------------------
+    def run(self, requests, clock=time.perf_counter, replay: bool = False) -> ServeReport:
+        """Serve `requests` (sorted by arrival).  With replay=False arrivals
+        follow the wall clock (idle periods are waited out); with replay=True
+        the run starts each request as soon as possible in arrival order."""
+        pending = list(requests)
+        report = ServeReport()
+        t0 = clock()
+        i = 0
+        while i < len(pending) or self.inflight:
+            now = clock() - t0
+            while i < len(pending) and (replay or pending[i].arrival <= now):
+                if not self._try_admit(pending[i], now):
+                    break
+                i += 1
+            if not self.inflight:
+                if i >= len(pending):
+                    break
+                if replay or pending[i].arrival <= clock() - t0:
+                    # it arrived, nothing runs, and it still does not fit
+                    raise RuntimeError(f"request {pending[i].rid} can never be admitted "
+                                       "(larger than the server's capacity)")
+                wait = pending[i].arrival - (clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.001))
+                continue
+            done = self.engine.step(self.levels_per_step)
+            report.steps += 1
+            now = clock() - t0
+            for slot in done:
+                report.completed.append(self._complete(slot, now))
+        report.wall = clock() - t0
+        return report
+
+
+def poisson_requests(rate_qps: float, count: int, instances: dict, bfs_share: float = 0.7,
+                     upload_graphs=None, upload_share: float = 0.0, seed: int = 171100231,
+                     sources=None):
+    """A seeded Poisson stream: exponential inter-arrival times at rate_qps,
+    BFS with probability bfs_share, target instance uniform over the resident
+    ones (or an uploaded graph with probability upload_share), source uniform
+    over the instance's listed sources (or its nodes)."""
+    rng = np.random.default_rng(seed)
+    names = sorted(instances)
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += rng.exponential(1.0 / rate_qps)
+        kind = KIND_BFS if rng.random() < bfs_share else KIND_SSSP
+        if upload_graphs and rng.random() < upload_share:
+            g = upload_graphs[int(rng.integers(len(upload_graphs)))]
+            out.append(Request(rid, t, kind, None, int(rng.integers(g.n)), graph=g))
+        else:
+            name = names[int(rng.integers(len(names)))]
+            inst = instances[name]
+            if sources is not None and name in sources:
+                src = int(sources[name][int(rng.integers(len(sources[name])))])
+            else:
+                src = int(rng.integers(inst.hi - inst.lo))
+            out.append(Request(rid, t, kind, name, src))
+    return out
+
+
+class UploadArena:
+    """Fixed regions at the end of the packed CSR for per-request graphs.
+
+    Region r owns nodes [node_base + r*node_cap, ... + node_cap) and arcs
+    [arc_base + r*arc_cap, ... + arc_cap).  A loaded graph takes the first n'
+    nodes (n' < node_cap) and m' <= arc_cap arcs; the region's last node is a
+    sink that owns the unused arcs, so the packed offsets stay monotone for
+    any loaded graph.  No arc leads to the sink or to the unused nodes, so a
+    query on [lo, lo + n') never sees them.
+    """
+
+    def __init__(self, dg, node_base: int, arc_base: int, regions: int, node_cap: int,
+                 arc_cap: int):
+        self.dg = dg
+        self.node_base, self.arc_base = int(node_base), int(arc_base)
+        self.regions, self.node_cap, self.arc_cap = int(regions), int(node_cap), int(arc_cap)
+        self.free = list(range(self.regions))
+
+    @staticmethod
+    def empty_arrays(regions: int, node_cap: int, arc_cap: int, node_base: int, arc_base: int):
+        """Host CSR pieces for `regions` empty regions: offsets (without the
+        final entry), cols, weights, to append after the resident graphs."""
+        off = np.empty(regions * node_cap, dtype=np.int64)
+        cols = np.empty(regions * arc_cap, dtype=np.int32)
+        for r in range(regions):
+            a0 = arc_base + r * arc_cap
+            off[r * node_cap: (r + 1) * node_cap] = a0  # all arcs belong to the sink
+            cols[r * arc_cap: (r + 1) * arc_cap] = node_base + (r + 1) * node_cap - 1
+        return off, cols, np.ones(regions * arc_cap, dtype=np.uint32)
+
+    def acquire(self):
+        return self.free.pop(0) if self.free else None
+
+    def release(self, region: int) -> None:
+        self.free.append(region)
+        self.free.sort()
+
+    def load(self, region: int, g) -> tuple:
+        import torch
+
+        if g.n >= self.node_cap or g.m > self.arc_cap:
+            raise ValueError(f"graph with n={g.n}, m={g.m} exceeds the upload region")
+        lo = self.node_base + region * self.node_cap
+        a0 = self.arc_base + region * self.arc_cap
+        off = np.full(self.node_cap, a0 + g.m, dtype=np.int64)
+        off[: g.n + 1] = a0 + g.offsets.astype(np.int64)
+        dev = self.dg.offsets.device
+        self.dg.offsets[lo: lo + self.node_cap].copy_(torch.from_numpy(off.astype(np.int32)).to(dev))
+        if g.m:
+            self.dg.cols[a0: a0 + g.m].copy_(
+                torch.from_numpy((g.cols.astype(np.int64) + lo).astype(np.int32)).to(dev))
+            self.dg.weights[a0: a0 + g.m].copy_(torch.from_numpy(g.weights.view(np.int32)).to(dev))
+        return lo, lo + g.n, g.m

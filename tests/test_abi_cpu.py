@@ -105,3 +105,31 @@ def test_validate_csr_argument_errors():
     assert lib.lbg_validate_csr(FAKE, FAKE, 5, -2, WS, 1 << 20, None) == lbgmod.ERANGE
     assert lib.lbg_validate_csr(None, FAKE, 5, 5, WS, 1 << 20, None) == lbgmod.EINVAL
     assert lib.lbg_validate_csr(FAKE, FAKE, 5, 5, WS, 8, None) == lbgmod.ENOMEM
+
+
+def test_batch_workspace_and_argument_errors():
+    T = 256  # batched tile
+    al = lambda x: (x + 255) // 256 * 256
+    Q, rows, arcs = 7, 5000, 123457
+    tiles = (arcs + T - 1) // T + 2
+    exp = al(128 + 8 * 128) + al(32 * Q) + al(8 * rows) + 2 * (4 * al(4 * rows) + al(4 * tiles))
+    assert lbgmod.batch_workspace_bytes(Q, rows, arcs) == exp
+    assert lbgmod.batch_workspace_bytes(0, rows, arcs) == 0
+    assert lbgmod.batch_workspace_bytes(Q, 2**31, arcs) == 0
+    assert lbgmod.batch_workspace_bytes(Q, rows, 2**32) == 0
+
+    def solve(queries, n=100, m=50, rows=1000, arcs=100, ws_bytes=1 << 40):
+        arr, _ = lbgmod.batch_queries(queries)
+        return lib.lbg_batch_solve(FAKE, FAKE, FAKE, n, m, arr, len(arr), FAKE, rows, arcs, WS,
+                                   ws_bytes, None, None)
+
+    ok = (5, 0, 10, 0, 0)
+    assert solve([(11, 0, 10, 0, 0)]) == lbgmod.ERANGE       # src outside its instance
+    assert solve([(5, 0, 101, 0, 0)]) == lbgmod.ERANGE       # instance beyond n
+    assert solve([(5, 6, 6, 0, 0)]) == lbgmod.ERANGE         # empty instance
+    assert solve([(5, 0, 10, 2, 0)]) == lbgmod.EINVAL        # unknown kind
+    assert solve([ok, (5, 0, 10, 1, 995)]) == lbgmod.ERANGE  # row beyond total_rows
+    assert solve([ok], ws_bytes=64) == lbgmod.ENOMEM
+    assert solve([ok], n=0) == lbgmod.EINVAL
+    assert lib.lbg_batch_solve(FAKE, FAKE, FAKE, 100, 50, None, 0, FAKE, 10, 10, WS, 1 << 40,
+                               None, None) == lbgmod.EINVAL

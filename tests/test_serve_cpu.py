@@ -1,0 +1,171 @@
+"""Serving scheduler on the CPU: admission by slots / rows / upload regions,
+FCFS order, resource reuse, Poisson replay and result identity, with a fake
+engine whose 'kernels' are the CPU oracle (no GPU)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from paper_1711_00231_amd import serve
+
+torch = pytest.importorskip("torch")
+O = oracle.get()
+
+
+class _Rows:
+    def __init__(self, n):
+        self.a = np.full(n, -1, dtype=np.int32)
+
+    def __getitem__(self, sl):
+        return torch.from_numpy(self.a[sl])
+
+
+class FakeEngine:
+    """Engine stand-in: a query finishes `lag` steps after it was submitted
+    (more for bigger instances); its row is then the oracle's answer on the
+    packed graph restricted to its instance."""
+
+    def __init__(self, packed, max_queries, max_rows, lag=2):
+        self.g = packed
+        self.max_queries, self.max_rows = max_queries, max_rows
+        self.rows = _Rows(max_rows)
+        self.slots = {}
+        self.lag = lag
+        self.tick = 0
+        self.max_inflight = 0
+
+    def submit(self, src, lo, hi, kind, out_off):
+        if len(self.slots) >= self.max_queries:
+            return -1
+        for (s2, lo2, hi2, k2, o2, t2) in self.slots.values():  # rows never overlap
+            assert out_off + hi - lo <= o2 or o2 + hi2 - lo2 <= out_off
+        slot = min(set(range(self.max_queries)) - set(self.slots))
+        self.slots[slot] = (src, lo, hi, kind, out_off, self.tick)
+        self.max_inflight = max(self.max_inflight, len(self.slots))
+        return slot
+
+    def step(self, levels=1):
+        self.tick += 1
+        done = []
+        for slot, (src, lo, hi, kind, off, t) in list(self.slots.items()):
+            if self.tick - t >= self.lag + (hi - lo) // 2000:
+                sub_off = self.g.offsets[lo: hi + 1].astype(np.int64)
+                base = sub_off[0]
+                cols = self.g.cols[base: sub_off[-1]] - lo
+                w = self.g.weights[base: sub_off[-1]]
+                sub = sub_off - base
+                if kind == serve.KIND_BFS:
+                    r = O.bfs(sub, cols, src - lo)
+                else:
+                    r = O.dijkstra(sub, cols, w, src - lo).view(np.int32)
+                self.rows.a[off: off + hi - lo] = r
+                done.append(slot)
+                self.slots[slot] = self.slots[slot] + ("done",)
+        return done
+
+    def release(self, slot):
+        assert len(self.slots[slot]) == 7, "released before finishing"
+        del self.slots[slot]
+
+
+def _setup():
+    gs = [graphgen.uniform(n=3000, k=6, wlo=1, whi=50, salt=1), graphgen.rmat(11, salt=2),
+          graphgen.grid(40, salt=3)]
+    u, nb, eb = graphgen.pack(gs)
+    inst = {f"g{i}": serve.Instance(int(nb[i]), int(nb[i + 1]), int(eb[i + 1] - eb[i]))
+            for i in range(len(gs))}
+    return gs, u, inst
+
+
+def _check_results(report, gs):
+    for r in report.completed:
+        g = gs[int(r.instance[1:])]
+        exp = O.bfs(g.offsets, g.cols, r.src) if r.kind == serve.KIND_BFS else \
+            O.dijkstra(g.offsets, g.cols, g.weights, r.src).view(np.int32)
+        assert np.array_equal(r.result, exp), r.rid
+
+
+def test_row_allocator():
+    a = serve.RowAllocator(100)
+    x, y, z = a.alloc(30), a.alloc(30), a.alloc(30)
+    assert (x, y, z) == (0, 30, 60) and a.alloc(20) is None
+    a.release(30, 30)
+    assert a.alloc(40) is None and a.alloc(25) == 30
+    a.release(0, 30)
+    a.release(30, 25)
+    a.release(60, 30)
+    assert a.free == [(0, 100)] and a.in_use == 0
+
+
+def test_replay_all_complete_fcfs_and_identical():
+    gs, u, inst = _setup()
+    eng = FakeEngine(u, max_queries=4, max_rows=6000)
+    reqs = serve.poisson_requests(1e4, 60, inst, seed=5)
+    rep = serve.Server(eng, inst, keep_results=True).run(reqs, replay=True)
+    assert len(rep.completed) == 60
+    adm = [r.admitted for r in sorted(rep.completed, key=lambda r: r.rid)]
+    assert adm == sorted(adm), "admission is first-come first-served"
+    assert eng.max_inflight <= 4 and not eng.slots
+    _check_results(rep, gs)
+    s = rep.summary()
+    assert s["requests"] == 60 and s["p99_ms"] >= s["p50_ms"] >= 0
+
+
+def test_capacity_blocks_but_never_starves():
+    gs, u, inst = _setup()
+    # rows for only one big instance at a time
+    eng = FakeEngine(u, max_queries=8, max_rows=3100)
+    reqs = serve.poisson_requests(1e5, 25, inst, seed=9)
+    rep = serve.Server(eng, inst, keep_results=True).run(reqs, replay=True)
+    assert len(rep.completed) == 25
+    _check_results(rep, gs)
+
+
+def test_too_large_request_raises():
+    gs, u, inst = _setup()
+    eng = FakeEngine(u, max_queries=2, max_rows=100)
+    reqs = [serve.Request(0, 0.0, serve.KIND_BFS, "g0", 0)]
+    with pytest.raises(RuntimeError, match="never be admitted"):
+        serve.Server(eng, inst).run(reqs, replay=True)
+
+
+def test_wall_clock_arrivals():
+    gs, u, inst = _setup()
+    eng = FakeEngine(u, max_queries=4, max_rows=8000)
+    reqs = serve.poisson_requests(400.0, 12, inst, seed=2)
+    rep = serve.Server(eng, inst).run(reqs)
+    assert len(rep.completed) == 12
+    assert all(r.done >= r.arrival and r.admitted >= r.arrival - 1e-9 for r in rep.completed)
+
+
+def test_upload_region_layout_matches_graph():
+    """A graph loaded into an upload region of the packed CSR has exactly its
+    own BFS/SSSP answers on [lo, lo + n') (CPU tensors stand in for HBM)."""
+    from paper_1711_00231_amd.serve import UploadArena
+
+    base = graphgen.rmat(9, salt=4)
+    NC, MC, R = 600, 4000, 3
+    off_e, cols_e, w_e = UploadArena.empty_arrays(R, NC, MC, base.n, base.m)
+    p_off = np.concatenate([base.offsets[:-1].astype(np.int64), off_e, [base.m + R * MC]])
+    p_cols = np.concatenate([base.cols, cols_e])
+    p_w = np.concatenate([base.weights, w_e])
+
+    class DG:  # minimal device-graph stand-in on the CPU
+        offsets = torch.from_numpy(p_off.astype(np.int32))
+        cols = torch.from_numpy(p_cols.astype(np.int32))
+        weights = torch.from_numpy(p_w.view(np.int32))
+
+    arena = UploadArena(DG, base.n, base.m, R, NC, MC)
+    for salt, region in ((1, arena.acquire()), (2, arena.acquire()), (3, 0)):
+        g = graphgen.uniform(n=450 + 40 * salt, k=7, wlo=1, whi=30, salt=salt)
+        lo, hi, arcs = arena.load(region, g)
+        po = DG.offsets.numpy().astype(np.int64)
+        assert np.all(np.diff(po) >= 0) and po[-1] == len(p_cols)
+        sub = po[lo: hi + 1] - po[lo]
+        sc = DG.cols.numpy()[po[lo]: po[hi]] - lo
+        sw = DG.weights.numpy().view(np.uint32)[po[lo]: po[hi]]
+        for s in (0, 17):
+            assert np.array_equal(O.bfs(sub, sc, s), O.bfs(g.offsets, g.cols, s))
+            assert np.array_equal(O.dijkstra(sub, sc, sw, s), O.dijkstra(g.offsets, g.cols, g.weights, s))
+        # the whole packed graph stays valid (oracle rejects bad CSR)
+        O.bfs(po, DG.cols.numpy(), 0)
