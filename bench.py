@@ -1,19 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: level-synchronous BFS and SSSP on one MI355X.
 
-Workload (default): R-MAT scale 22, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05),
+Default workload: R-MAT scale 22, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05),
 relabelled, symmetrised, duplicates and self-loops removed (n = 4,194,304,
 m = 128,307,136 arcs), uint32 weights U[1,255], 64 seeded non-isolated
 sources.  One step = BFS then SSSP from each of `--sources-per-step` sources
-(cycling through the 64), through the C ABI, with the graph resident in HBM.
+(cycling through the 64) through the C ABI, graph resident in HBM.
 
-Throughput: GTEPS = arcs leaving reached nodes (the CSR arcs a traversal
-scans) / wall time, summed over BFS and SSSP solves; the Graph500-style
-figure (half of that on a symmetrised graph) is printed beside it.
+value: GTEPS = arcs leaving reached nodes (the CSR arcs a traversal scans)
+per second of wall time, summed over the step's BFS and SSSP solves; the
+Graph500-style figure (half of that on a symmetrised graph) is printed beside.
 
-Roofline: the dominant frontier-expansion kernel's algorithmic bytes per
-launch / its average launch duration, timed live with HIP events on the
-stream it runs on, against 8 TB/s HBM.  Algorithmic bytes per launch:
+roofline: the dominant frontier-expansion kernel's algorithmic bytes per
+launch over its average launch duration, timed live with HIP events on the
+stream it runs on, against 8 TB/s HBM.  Algorithmic bytes:
   BFS  8 B per arc scanned (column id + destination state) + 20 B per node
        discovered (two offsets, level write, worklist write and read);
   SSSP 12 B per relaxation (column id, weight, destination distance) + 4 B
@@ -21,6 +21,15 @@ stream it runs on, against 8 TB/s HBM.  Algorithmic bytes per launch:
 
 cpu_baseline: the CPU oracle (queue BFS + binary-heap Dijkstra, one thread)
 on a bounded sample of the same sources.
+
+batched / serving (extra objects on the same line; full sizes with
+--mode batch / --mode serve):
+  batched: the same queries as one lbg_batch_solve call vs one plain call
+  per query, over packed instances of uneven size.
+  serving: a Poisson stream of BFS/SSSP requests (70/30) over resident
+  graphs plus per-request uploaded graphs, served with continuous batching;
+  p50/p99 latency at fractions of the saturation rate of plain per-query
+  launches.
 """
 from __future__ import annotations
 
@@ -99,41 +108,13 @@ def cpu_baseline(g, srcs, budget_s):
         used += 1
         if t_total >= budget_s:
             break
-    return {"value": arcs / t_total / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+    return {"value": round(arcs / t_total / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"{used} source(s) of the same workload, BFS + Dijkstra each, "
                       f"{t_total:.1f} s single-threaded"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat22")
-    ap.add_argument("--strategy", default="balanced")
-    ap.add_argument("--sources-per-step", type=int, default=8)
-    ap.add_argument("--cpu-budget", type=float, default=15.0,
-                    help="seconds of oracle work for the cpu_baseline leg (0 = skip)")
-    ap.add_argument("--no-profile", action="store_true",
-                    help="do not bracket expansion launches with events (no roofline)")
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="after the timed region, copy a buffer of this many MiB three times "
-                         "(a plain copy kernel of known size, to scale rocprofv3 HBM counters)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(queries are independent; see DESIGN.md for how it would shard).", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    from paper_1711_00231_amd import lbg
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
+# ---------------------------------------------------------------- plain --
+def run_plain(args, lbg, torch, dev):
     t0 = time.perf_counter()
     g, srcs, desc, sym = make_workload(args.workload)
     log(f"workload {g.name}: n={g.n} m={g.m} built in {time.perf_counter() - t0:.1f}s")
@@ -189,20 +170,20 @@ def main():
     prof = {}
     if not args.no_profile:
         lbg.profile_enable(False, reset=False)
-        prof = {"bfs": lbg.profile_read(False), "sssp": lbg.profile_read(True)}
+        prof = {"bfs": lbg.profile_read("bfs"), "sssp": lbg.profile_read("sssp")}
     bfs_ms, sssp_ms = sum(lat["bfs"]), sum(lat["sssp"])
-    solve_s = elapsed
     n_solves = args.steps * per
-    bfs_arcs = sum(reach_arcs[s] for k in range(args.warmup, args.warmup + args.steps) for s in plan[k])
+    bfs_arcs = sum(reach_arcs[s] for k in range(args.warmup, args.warmup + args.steps)
+                   for s in plan[k])
 
     out = {
         "metric": METRIC,
-        "value": round(arcs_total / solve_s / 1e9, 4),
+        "value": round(arcs_total / elapsed / 1e9, 4),
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(solve_s * 1e3 / args.steps, 4),
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -213,41 +194,32 @@ def main():
                    "solves_timed": 2 * n_solves},
         "bfs_gteps": round(bfs_arcs / (bfs_ms / 1e3) / 1e9, 4),
         "sssp_gteps": round(bfs_arcs / (sssp_ms / 1e3) / 1e9, 4),
-        "graph500_gteps": round(arcs_total / solve_s / 1e9 / (2 if sym else 1), 4),
+        "graph500_gteps": round(arcs_total / elapsed / 1e9 / (2 if sym else 1), 4),
         "bfs_ms_p50": round(float(np.percentile(lat["bfs"], 50)), 4),
         "bfs_ms_p99": round(float(np.percentile(lat["bfs"], 99)), 4),
         "sssp_ms_p50": round(float(np.percentile(lat["sssp"], 50)), 4),
         "sssp_ms_p99": round(float(np.percentile(lat["sssp"], 99)), 4),
-        "wall_s_timed_region": round(elapsed, 4),
     }
     if not args.no_profile:
         kern = {}
         for kind in ("bfs", "sssp"):
             p = prof[kind]
             nl = p["launches"] + p["empty_launches"]
-            byt = algorithmic_bytes(kind, p)
-            kern[kind] = {
-                "kernel": f"k_expand_{args.strategy}<{'true' if kind == 'sssp' else 'false'}>",
-                "launches": nl, "kernel_ms": p["kernel_ms"] + p["empty_ms"],
-                "bytes": byt, "edges_scanned": p["edges_scanned"],
-                "avg_launch_us": (p["kernel_ms"] + p["empty_ms"]) * 1e3 / max(nl, 1),
-            }
+            kname = "balanced" if args.strategy == "auto" else args.strategy
+            kern[kind] = {"kernel": f"k_expand_{kname}<{'true' if kind == 'sssp' else 'false'}>",
+                          "launches": nl, "kernel_ms": p["kernel_ms"] + p["empty_ms"],
+                          "bytes": algorithmic_bytes(kind, p)}
         dom = max(kern, key=lambda k: kern[k]["kernel_ms"])
-        kd = kern[dom]
-        achieved = kd["bytes"] / (kd["kernel_ms"] / 1e3) / 1e9
-        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": None, "kernel": kd["kernel"],
-                           "avg_launch_us": round(kd["avg_launch_us"], 3),
-                           "bytes_per_launch": round(kd["bytes"] / max(kd["launches"], 1))}
-        other = "bfs" if dom == "sssp" else "sssp"
-        ko = kern[other]
-        out["roofline_other"] = {"kernel": ko["kernel"],
-                                 "achieved": round(ko["bytes"] / (ko["kernel_ms"] / 1e3) / 1e9, 2),
-                                 "avg_launch_us": round(ko["avg_launch_us"], 3),
-                                 "bytes_per_launch": round(ko["bytes"] / max(ko["launches"], 1))}
+        for kind, kd in kern.items():
+            achieved = kd["bytes"] / (kd["kernel_ms"] / 1e3) / 1e9
+            obj = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                   "traffic": None, "kernel": kd["kernel"], "launches": kd["launches"],
+                   "avg_launch_us": round(kd["kernel_ms"] * 1e3 / max(kd["launches"], 1), 3),
+                   "bytes_per_launch": round(kd["bytes"] / max(kd["launches"], 1))}
+            out["roofline" if kind == dom else "roofline_" + kind] = obj
         out["kernel_share_of_wall"] = round(
-            (kern["bfs"]["kernel_ms"] + kern["sssp"]["kernel_ms"]) / (solve_s * 1e3), 4)
+            (kern["bfs"]["kernel_ms"] + kern["sssp"]["kernel_ms"]) / (elapsed * 1e3), 4)
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
         a_ = torch.empty(nb // 4, dtype=torch.int32, device=dev).fill_(1)
@@ -257,6 +229,197 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nb
         del a_, b_
+    return out, g, srcs
+
+
+# -------------------------------------------------------------- batched --
+def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
+    """The same 2 x sources x count queries solved as one batch and as
+    single-query calls; GTEPS over arcs leaving reached nodes."""
+    import graphgen
+
+    t0 = time.perf_counter()
+    gs = graphgen.batch_instances(count, hi_exp=hi_exp)
+    u, nb, eb = graphgen.pack(gs)
+    log(f"batch: {count} instances, n={u.n} m={u.m} built in {time.perf_counter() - t0:.1f}s")
+    dg = lbg.DeviceGraph.from_numpy(u.offsets, u.cols, u.weights, device=dev)
+    singles = [lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev) for g in gs]
+    queries = []
+    for i, g in enumerate(gs):
+        for s in graphgen.sources(g, sources_per_instance, graphgen.FAMILY_BATCH, salt=i):
+            for kind in (lbg.KIND_BFS, lbg.KIND_SSSP):
+                queries.append((int(nb[i] + s), int(nb[i]), int(nb[i + 1]), kind))
+    ws = lbg.Workspace(dev)
+    ws1 = lbg.Workspace(dev)
+    out = lbg.batch_solve(dg, queries, workspace=ws)  # warm-up + reached-arc count
+    deg = torch.from_numpy(np.diff(u.offsets.astype(np.int64))).to(dev)
+    reached = 0
+    off = 0
+    for q in queries:
+        row = out[off: off + q[2] - q[1]]
+        unreached = lbg.BFS_INF if q[3] == lbg.KIND_BFS else -1  # UINT32_MAX as int32
+        reached += int(deg[q[1]: q[2]][row != unreached].sum().item())
+        off += q[2] - q[1]
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lbg.batch_solve(dg, queries, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t)
+    # plain: one call per query on the query's own instance graph
+    idx = np.searchsorted(nb, [q[0] for q in queries], side="right") - 1
+    outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in gs]
+    for q, i in zip(queries[:64], idx[:64]):  # warm-up
+        f = lbg.bfs if q[3] == lbg.KIND_BFS else lbg.sssp
+        f(singles[i], q[0] - q[1], out=outs[i], workspace=ws1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lat = []
+    for q, i in zip(queries, idx):
+        f = lbg.bfs if q[3] == lbg.KIND_BFS else lbg.sssp
+        t1 = time.perf_counter()
+        f(singles[i], q[0] - q[1], out=outs[i], workspace=ws1)
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    bt = min(tb)
+    return {"queries": len(queries), "instances": count, "n": u.n, "m": u.m,
+            "batched_s": round(bt, 5), "plain_s": round(tp, 5),
+            "batched_gteps": round(reached / bt / 1e9, 4), "plain_gteps": round(reached / tp / 1e9, 4),
+            "speedup": round(tp / bt, 3),
+            "plain_query_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
+            "plain_query_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 4),
+            "workload": f"{count} instances (half R-MAT scale U[10,{hi_exp}] ef 16 symmetrised, "
+                        f"half uniform n=2^U(10,{hi_exp}) 8 out-arcs), weights U[1,255], "
+                        f"{sources_per_instance} sources each, BFS + SSSP"}
+
+
+# -------------------------------------------------------------- serving --
+def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_count=8):
+    import graphgen
+    from paper_1711_00231_amd import serve
+
+    t0 = time.perf_counter()
+    resident = [graphgen.rmat(s, salt=50 + s) for s in scales]
+    uploads = [graphgen.uniform(n=int(2 ** e), k=8, wlo=1, whi=255, salt=60 + i)
+               for i, e in enumerate(np.linspace(12, 16, upload_count))]
+    u, nb, eb = graphgen.pack(resident)
+    NC, MC, R = (1 << 16) + 1, (1 << 16) * 8, 8
+    off_e, cols_e, w_e = serve.UploadArena.empty_arrays(R, NC, MC, u.n, u.m)
+    off = np.concatenate([u.offsets[:-1].astype(np.int64), off_e, [u.m + R * MC]])
+    dg = lbg.DeviceGraph.from_numpy(off, np.concatenate([u.cols, cols_e]),
+                                    np.concatenate([u.weights, w_e]), device=dev)
+    del off, off_e, cols_e, w_e
+    log(f"serve: resident scales {scales}, n={u.n} m={u.m} built in {time.perf_counter() - t0:.1f}s")
+    inst = {f"rmat{s}": serve.Instance(int(nb[i]), int(nb[i + 1]), int(eb[i + 1] - eb[i]))
+            for i, s in enumerate(scales)}
+    srcs = {f"rmat{s}": graphgen.sources(g, 64, graphgen.FAMILY_SERVE, salt=s)
+            for s, g in zip(scales, resident)}
+    # saturation of plain per-query launches: mean service time of the mix
+    singles = {f"rmat{s}": lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
+               for s, g in zip(scales, resident)}
+    up_dev = {id(g): lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
+              for g in uploads}
+    ws1 = lbg.Workspace(dev)
+    probe = serve.poisson_requests(1.0, 60, inst, upload_graphs=uploads, upload_share=0.25,
+                                   seed=11, sources=srcs)
+    svc = []
+    for r in probe:
+        gd = singles[r.instance] if r.instance else up_dev[id(r.graph)]
+        f = lbg.bfs if r.kind == serve.KIND_BFS else lbg.sssp
+        f(gd, r.src, workspace=ws1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        f(gd, r.src, workspace=ws1)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t)
+    sat = 1.0 / float(np.mean(svc))
+    del singles, up_dev, ws1
+    max_rows = 6 * max(g.n for g in resident) + 16 * NC
+    eng = lbg.Engine(dg, max_queries=64, max_rows=max_rows,
+                     max_level_arcs=min(2**32 - 1, 8 * (u.m + R * MC)))
+    points = []
+    for frac in fractions:
+        qps = sat * frac
+        reqs = serve.poisson_requests(qps, requests_per_point, inst, upload_graphs=uploads,
+                                      upload_share=0.25, seed=int(frac * 1000), sources=srcs)
+        arena = serve.UploadArena(dg, u.n, u.m, R, NC, MC)
+        rep = serve.Server(eng, inst, upload=arena).run(reqs)
+        s = rep.summary()
+        s["offered_qps"] = round(qps, 2)
+        s["fraction_of_plain_saturation"] = frac
+        points.append(s)
+        log(f"serve {frac:.2f} x saturation: {s}")
+    eng.close()
+    return {"plain_saturation_qps": round(sat, 2),
+            "plain_service_ms_p50": round(float(np.percentile(svc, 50)) * 1e3, 4),
+            "plain_service_ms_p99": round(float(np.percentile(svc, 99)) * 1e3, 4),
+            "points": points,
+            "workload": f"resident R-MAT scales {list(scales)} (ef 16, symmetrised, weights "
+                        f"U[1,255]) + per-request uploaded uniform graphs n in [2^12, 2^16]; "
+                        f"Poisson arrivals, 70% BFS / 30% SSSP, 25% uploads; "
+                        f"{requests_per_point} requests per point; gteps counts instance arcs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--strategy", default="balanced")
+    ap.add_argument("--sources-per-step", type=int, default=8)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle work for the cpu_baseline leg (0 = skip)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not bracket expansion launches with events (no roofline)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain mode: skip the compact batched and serving measurements")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed region, copy a buffer of this many MiB three times "
+                         "(a plain copy kernel of known size, to scale rocprofv3 HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(queries are independent; DESIGN.md describes how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1711_00231_amd import lbg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.mode == "batch":
+        res = run_batch(lbg, torch, dev, count=256, sources_per_instance=4, hi_exp=18)
+        print(json.dumps({"metric": "batched vs plain GTEPS", "value": res["batched_gteps"],
+                          "unit": "GTEPS", "n_gpus": 1, "higher_is_better": True,
+                          "dtype": "u32", "data": "synthetic", "vs_baseline": None,
+                          "config": {"workload": res["workload"]}, "batched": res}), flush=True)
+        return
+    if args.mode == "serve":
+        res = run_serve(lbg, torch, dev, scales=(20, 22, 24),
+                        fractions=(0.25, 0.5, 0.75, 1.0, 1.25), requests_per_point=2000)
+        p99 = max(p["p99_ms"] for p in res["points"])
+        print(json.dumps({"metric": "served p99 latency (ms) over a QPS sweep", "value": p99,
+                          "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "u32",
+                          "data": "synthetic", "vs_baseline": None,
+                          "config": {"workload": res["workload"]}, "serving": res}), flush=True)
+        return
+
+    out, g, srcs = run_plain(args, lbg, torch, dev)
+    if not args.no_extras:
+        log("compact batched comparison")
+        out["batched"] = run_batch(lbg, torch, dev, count=64, sources_per_instance=4, hi_exp=16)
+        log("compact serving run")
+        out["serving"] = run_serve(lbg, torch, dev, scales=(18, 20), fractions=(0.5, 1.0),
+                                   requests_per_point=300, upload_count=4)
     if args.cpu_budget > 0:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(g, srcs, args.cpu_budget)
