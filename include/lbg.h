@@ -141,8 +141,12 @@ typedef struct {
   int64_t atomics;           /* device-scope atomics issued on node state */
 } lbg_profile;
 
-/* Totals since the last reset of BFS solves (which = 0), SSSP solves (1) or
- * batched solves (2). */
+/* Totals since the last reset of the one-level launches of BFS solves
+ * (which = 0), SSSP solves (1) or batched solves (2), and of the
+ * small-frontier launches of BFS (3) and SSSP (4) solves (the
+ * single-workgroup level loop that balanced solves switch to while a level
+ * has at most 4000 entries and 16384 edges; `launches` counts launches, the
+ * work counters cover every level they ran, empty_* stay 0). */
 void lbg_profile_read(int32_t which, lbg_profile* out);
 
 /* ------------------------------------------------------------------------

@@ -115,7 +115,21 @@ int resident_grid(K kernel) {
 
 struct Grids {
   int bal[2][2], node[2], edge[2], multi[2];  // bal[is_sssp][narrow], multi[narrow]
+  bool small[2][2];                           // small-frontier kernel fits the device
 };
+
+// The small-frontier kernel holds its frontier in LDS (about 100 KiB for
+// SSSP); use it only where the device grants a workgroup that much.
+template <typename K>
+bool fits_lds(K kernel) {
+  int dev = 0, max_lds = 0;
+  hipFuncAttributes fa{};
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) != hipSuccess)
+    return false;
+  return fa.sharedSizeBytes <= static_cast<size_t>(max_lds) && fa.maxThreadsPerBlock >= lbg::kSmallBlock;
+}
 
 const Grids& grids() {
   static std::mutex mu;
@@ -135,6 +149,10 @@ const Grids& grids() {
     g[dev].edge[1] = resident_grid(lbg::k_expand_edge<true>);
     g[dev].multi[0] = resident_grid(lbg::k_expand_balanced<true, false, true>);
     g[dev].multi[1] = resident_grid(lbg::k_expand_balanced<true, true, true>);
+    g[dev].small[0][0] = fits_lds(lbg::k_expand_small<false, false>);
+    g[dev].small[0][1] = fits_lds(lbg::k_expand_small<false, true>);
+    g[dev].small[1][0] = fits_lds(lbg::k_expand_small<true, false>);
+    g[dev].small[1][1] = fits_lds(lbg::k_expand_small<true, true>);
     done[dev] = true;
   }
   return g[dev];
@@ -145,7 +163,9 @@ int grid_blocks() { return grids().bal[0][1]; }
 // Host side of the profiling counters (see lbg_profile_enable).
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-lbg_profile g_prof[3]{};  // [0] BFS, [1] SSSP, [2] batched solves
+// [0] BFS, [1] SSSP, [2] batched solves (one-level launches); [3] BFS,
+// [4] SSSP levels run by the small-frontier kernel
+lbg_profile g_prof[5]{};
 
 struct PinnedCtl {
   Ctl* p = nullptr;
@@ -155,6 +175,7 @@ struct PinnedCtl {
 };
 thread_local PinnedCtl g_pinned;
 thread_local std::vector<hipEvent_t> g_events;
+thread_local std::vector<int64_t> g_event_level;  // per event pair: level, or -1 = small-frontier launch
 
 Ctl* pinned_ctl() {
   if (!g_pinned.p) {
@@ -174,6 +195,7 @@ hipEvent_t event_at(size_t i) {
   return g_events[i];
 }
 
+// Sum of one per-XCD stats slot.
 int64_t xsum(const Ctl* c, int k) {
   int64_t t = 0;
   for (int x = 0; x < lbg::kXcds; ++x) t += static_cast<int64_t>(c->xstat[x][k]);
@@ -303,48 +325,87 @@ int solve(const Problem& P) {
     }
   };
 
-  // Level loop: enqueue a batch of levels back to back (each launch reads its
-  // own work size on the device), then read the tail of the next level once.
-  uint32_t L = 0;
+  // Level loop.  One-level launches are enqueued in batches (each launch
+  // reads its own work size on the device) and the host reads the control
+  // block once per batch.  When the next level is small (at most kSmallF
+  // entries and kSmallE edges) the balanced strategy hands the following
+  // levels to the single-workgroup kernel, which keeps going on the device
+  // until a level outgrows those limits or the worklist empties; the host
+  // then resumes from ctl->levels, the next level to expand.
+  const bool small_ok = strat == LBG_BALANCED && GR.small[sv][nw];
+  uint32_t L = 0, L_prev = 0;
   uint32_t batch = 8;
+  bool small = false;
   size_t nev = 0;
+  g_event_level.clear();
   const uint64_t level_cap = static_cast<uint64_t>(P.n) + 2;
+  auto mark = [&]() -> int {
+    hipEvent_t e = event_at(nev++);
+    if (!e) return fail(LBG_EHIP, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(e, st));
+    return LBG_OK;
+  };
   for (;;) {
-    for (uint32_t k = 0; k < batch; ++k, ++L) {
-      if (profiling) {
-        hipEvent_t e = event_at(nev++);
-        if (!e) return fail(LBG_EHIP, "hipEventCreate failed");
-        HIP_TRY(hipEventRecord(e, st));
+    if (small) {
+      if (profiling && (rc = mark()) != LBG_OK) return rc;
+      const uint32_t max_levels = static_cast<uint32_t>(level_cap + 1 - L);
+      if (P.is_sssp) {
+        if (narrow) hipLaunchKernelGGL((lbg::k_expand_small<true, true>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
+        else hipLaunchKernelGGL((lbg::k_expand_small<true, false>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
+      } else {
+        if (narrow) hipLaunchKernelGGL((lbg::k_expand_small<false, true>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
+        else hipLaunchKernelGGL((lbg::k_expand_small<false, false>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
       }
-      launch(L);
       HIP_TRY(hipGetLastError());
       if (profiling) {
-        hipEvent_t e = event_at(nev++);
-        if (!e) return fail(LBG_EHIP, "hipEventCreate failed");
-        HIP_TRY(hipEventRecord(e, st));
+        if ((rc = mark()) != LBG_OK) return rc;
+        g_event_level.push_back(-1);
       }
+    } else {
+      for (uint32_t k = 0; k < batch; ++k, ++L) {
+        if (profiling && (rc = mark()) != LBG_OK) return rc;
+        launch(L);
+        HIP_TRY(hipGetLastError());
+        if (profiling) {
+          if ((rc = mark()) != LBG_OK) return rc;
+          g_event_level.push_back(L);
+        }
+      }
+      batch = std::min<uint32_t>(batch * 2, 64);
     }
     if (P.is_sssp) {
-      hipLaunchKernelGGL(lbg::k_sssp_finish, dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, L);
+      hipLaunchKernelGGL(lbg::k_sssp_finish, dim3(init_blocks), dim3(lbg::kBlock), 0, st, a);
       HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (host->error)
       return fail(LBG_EOVERFLOW, "device capacity guard tripped (flags 0x%x)", host->error);
-    if (static_cast<uint32_t>(host->ctr[L % 3]) == 0u) break;
+    L = host->levels;
+    const uint32_t ef = static_cast<uint32_t>(host->ctr[L % 3]);
+    if (ef == 0u) break;
     if (L > level_cap)
       return fail(LBG_EINTERNAL, "more than n + 1 levels; the CSR is probably malformed");
-    batch = std::min<uint32_t>(batch * 2, 64);
+    const bool was_small = small;
+    small = small_ok && ef <= lbg::kSmallE && (host->ctr[L % 3] >> 32) <= lbg::kSmallF &&
+            !(was_small && L == L_prev);  // a small step always advances; never spin
+    if (was_small && !small) batch = 8;
+    L_prev = L;
   }
 
+  const int64_t p_upd = xsum(host, 2), p_atom = xsum(host, 3);
   if (profiling) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     lbg_profile& gp = g_prof[P.is_sssp ? 1 : 0];
+    lbg_profile& pp = g_prof[P.is_sssp ? 4 : 3];
     for (size_t k = 0; k + 1 < nev; k += 2) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, g_events[k], g_events[k + 1]));
-      if (k / 2 < host->levels) {
+      const int64_t lv = g_event_level[k / 2];
+      if (lv < 0) {
+        pp.launches += 1;
+        pp.kernel_ms += ms;
+      } else if (lv < static_cast<int64_t>(host->levels)) {
         gp.launches += 1;
         gp.kernel_ms += ms;
       } else {
@@ -352,18 +413,24 @@ int solve(const Problem& P) {
         gp.empty_ms += ms;
       }
     }
-    gp.frontier_entries += static_cast<int64_t>(host->frontier_entries);
-    gp.edges_scanned += static_cast<int64_t>(host->edges_scanned);
+    const int64_t pfe = static_cast<int64_t>(host->p_frontier_entries);
+    const int64_t pes = static_cast<int64_t>(host->p_edges_scanned);
+    gp.frontier_entries += static_cast<int64_t>(host->frontier_entries) - pfe;
+    gp.edges_scanned += static_cast<int64_t>(host->edges_scanned) - pes;
     gp.updates += xsum(host, 0);
     gp.atomics += xsum(host, 1);
+    pp.frontier_entries += pfe;
+    pp.edges_scanned += pes;
+    pp.updates += p_upd;
+    pp.atomics += p_atom;
   }
   if (P.stats) {
     P.stats->levels = static_cast<int32_t>(host->levels);
     P.stats->reserved = 0;
     P.stats->frontier_entries = static_cast<int64_t>(host->frontier_entries);
     P.stats->edges_scanned = static_cast<int64_t>(host->edges_scanned);
-    P.stats->updates = xsum(host, 0);
-    P.stats->atomics = xsum(host, 1);
+    P.stats->updates = xsum(host, 0) + p_upd;
+    P.stats->atomics = xsum(host, 1) + p_atom;
   }
   return LBG_OK;
 }
@@ -867,11 +934,12 @@ const char* lbg_last_error(void) { return g_err; }
 void lbg_profile_enable(int32_t enable, int32_t reset) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof_on = enable != 0;
-  if (reset) g_prof[0] = g_prof[1] = g_prof[2] = lbg_profile{};
+  if (reset)
+    for (lbg_profile& p : g_prof) p = lbg_profile{};
 }
 
 void lbg_profile_read(int32_t which, lbg_profile* out) {
-  if (!out || which < 0 || which > 2) return;
+  if (!out || which < 0 || which > 4) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   *out = g_prof[which];
 }

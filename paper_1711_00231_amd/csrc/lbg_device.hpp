@@ -53,8 +53,12 @@ struct Ctl {
   unsigned long long edges_scanned;
   unsigned int csr_flags;     // lbg_validate_csr findings
   unsigned int pad0;
-  unsigned long long pad1[9];
-  unsigned long long xstat[kXcds][16];  // [x][0] updates, [x][1] global atomics issued
+  unsigned long long p_frontier_entries;  // the part of the two totals above
+  unsigned long long p_edges_scanned;     // done by the small-frontier kernel
+  unsigned long long pad1[7];
+  // [x][0] updates, [x][1] global atomics issued; [x][2], [x][3] the same for
+  // levels run by the small-frontier kernel
+  unsigned long long xstat[kXcds][16];
 };
 static_assert(sizeof(Ctl) == 128 + kXcds * 128, "Ctl layout");
 

@@ -41,24 +41,33 @@ constexpr uint32_t kBfsInf = 0x7fffffffu;
 constexpr uint32_t kSsspInf = 0xffffffffu;
 
 
-// Shared prologue: read this level's worklist size, clear the counter two
-// levels ahead, account the level.  Returns the packed (nodes, edges) tail.
+// Level bookkeeping, by one thread of the grid: clear the counter two levels
+// ahead (the one level L+1 appends to) and account level L.  kSmall: the
+// level runs in the small-frontier kernel, whose work is also counted apart.
+template <bool kSmall = false>
+__device__ __forceinline__ void level_account(const KArgs& a, uint32_t L, unsigned long long c) {
+  __hip_atomic_store(&a.ctl->ctr[(L + 2) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (static_cast<uint32_t>(c) != 0u) {
+    const unsigned long long fe = (c >> 32) ? (c >> 32) : static_cast<uint32_t>(c);
+    a.ctl->levels = L + 1;
+    a.ctl->frontier_entries += fe;
+    a.ctl->edges_scanned += static_cast<uint32_t>(c);
+    if (kSmall) {
+      a.ctl->p_frontier_entries += fe;
+      a.ctl->p_edges_scanned += static_cast<uint32_t>(c);
+    }
+  }
+}
+
+// Shared prologue of the one-level kernels: read this level's worklist size
+// and account the level.  Returns the packed (nodes, edges) tail.
 __device__ __forceinline__ unsigned long long level_begin(const KArgs& a, uint32_t L) {
   const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctl->ctr[(L + 2) % 3] = 0ull;
-    if (static_cast<uint32_t>(c) != 0u) {
-      a.ctl->levels = L + 1;
-      a.ctl->frontier_entries += (c >> 32) ? (c >> 32) : static_cast<uint32_t>(c);
-      a.ctl->edges_scanned += static_cast<uint32_t>(c);
-    }
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) level_account(a, L, c);
   return c;
 }
 
-// Block-level reduction of the per-thread counters, then one atomic per
-// block on this XCD's stats line.  Must be reached by the whole block.
 // BFS: next level's `seen` snapshot starts as this level's (whole grid).
 __device__ __forceinline__ void refresh_seen(const KArgs& a, uint32_t L) {
   const uint32_t* cur = a.seen[L & 1];
@@ -67,6 +76,8 @@ __device__ __forceinline__ void refresh_seen(const KArgs& a, uint32_t L) {
     nxt[k] = cur[k];
 }
 
+// Block-level reduction of the per-thread counters, then one atomic per
+// block on this XCD's stats line.  Must be reached by the whole block.
 __device__ __forceinline__ void add_stats(const KArgs& a, uint32_t upd, uint32_t atom) {
   if (!a.count_stats) return;  // kernel-argument uniform
   __shared__ uint32_t red[2][kWaves];
@@ -183,14 +194,18 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
     a.ctl->levels = 0u;
     a.ctl->frontier_entries = 0ull;
     a.ctl->edges_scanned = 0ull;
+    a.ctl->p_frontier_entries = 0ull;
+    a.ctl->p_edges_scanned = 0ull;
   }
   if (gid < kXcds * 16) a.ctl->xstat[gid / 16][gid % 16] = 0ull;
 }
 
-// SSSP epilogue: once the worklist of level L is empty, copy the distances
-// out of the packed state.  Launched after every batch of levels; exits at
-// once while work remains, so the host needs no extra synchronisation.
-__global__ __launch_bounds__(kBlock) void k_sssp_finish(KArgs a, uint32_t L) {
+// SSSP epilogue: once the worklist of the next level to expand (ctl->levels:
+// the last non-empty level + 1) is empty, copy the distances out of the
+// packed state.  Launched after every step of the level loop; exits at once
+// while work remains, so the host needs no extra synchronisation.
+__global__ __launch_bounds__(kBlock) void k_sssp_finish(KArgs a) {
+  const uint32_t L = __hip_atomic_load(&a.ctl->levels, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
   if (static_cast<uint32_t>(c) != 0u) return;
@@ -240,8 +255,21 @@ __device__ __forceinline__ void wave_sync() {
 
 // kMulti: batched solves (always the SSSP relaxation; BFS queries use unit
 // weights).  Entry (q, u) relaxes arc u -> v into row(q, v) = v + delta(q).
-template <bool kSssp, bool kNarrow, bool kMulti = false>
-__global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
+// Capacity check of a level's packed (nodes, edges) tail; block-uniform.
+template <bool kSssp, bool kMulti>
+__device__ __forceinline__ bool level_fits(const KArgs& a, unsigned long long c) {
+  constexpr uint32_t T = TileCfg<kSssp, kMulti>::kEdges;
+  const uint32_t Ef = static_cast<uint32_t>(c);
+  const uint32_t nf = static_cast<uint32_t>(c >> 32);
+  return nf <= a.node_cap &&
+         Ef <= (kMulti ? static_cast<unsigned long long>(a.tile_cap) * T : static_cast<unsigned long long>(a.m));
+}
+
+// One level of the balanced expansion by the whole grid (all threads of
+// every block must call it).  c = the level's packed tail, non-empty and
+// within capacity.
+template <bool kSssp, bool kNarrow, bool kMulti>
+__device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigned long long c) {
   static_assert(!kMulti || kSssp, "batched solves use the SSSP relaxation");
   constexpr int kItems = TileCfg<kSssp, kMulti>::kItems;
   constexpr uint32_t T = TileCfg<kSssp, kMulti>::kEdges;
@@ -250,15 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
   __shared__ uint32_t merge[2 * kWaves];
   __shared__ unsigned long long merge_base;
 
-  const unsigned long long c = level_begin(a, L);
   const uint32_t Ef = static_cast<uint32_t>(c);
   const uint32_t nf = static_cast<uint32_t>(c >> 32);
-  if (Ef == 0) return;
-  if (nf > a.node_cap ||
-      Ef > (kMulti ? static_cast<unsigned long long>(a.tile_cap) * T : static_cast<unsigned long long>(a.m))) {
-    if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrNodeCap);
-    return;
-  }
   const Frontier cur = a.fr[L & 1];
   Frontier nxt = a.fr[(L + 1) & 1];
   nxt.level = L + 1;
@@ -269,9 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
   uint32_t* fx = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
   const uint32_t* seen_cur = a.seen[L & 1];
   uint32_t* seen_nxt = a.seen[(L + 1) & 1];
-  // A frontier node's own distance comes from the distance half of the
-  // packed state (authoritative); the per-arc filter reads the output array.
-  const uint32_t* dist_hi = reinterpret_cast<const uint32_t*>(a.dstate) + 1;
+  // A frontier node's own distance comes from the packed state
+  // (authoritative); the per-arc filter reads the output array.
   const uint32_t state_len = kMulti ? a.rows : a.n;
   uint32_t upd = 0, atom = 0, qcount = 0;
   if (!kSssp) refresh_seen(a, L);
@@ -317,8 +337,18 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
           }
           if (kSssp) {
             const uint32_t row = static_cast<uint32_t>(node + delta);
-            if (row < state_len) w.du[j] = *at<kNarrow>(dist_hi, 2u * row);
-            else { w.du[j] = kSsspInf; bad = true; }
+            if (row < state_len) {
+              // A node that already improved during this launch is queued
+              // for the next iteration with a distance at least as good, and
+              // its arcs are relaxed there: skip them here (du = infinity
+              // marks the entry as skipped).  The state never moves back, so
+              // a stale read can only miss a skip, never invent one.
+              const unsigned long long sv = *at<kNarrow>(static_cast<const unsigned long long*>(a.dstate), row);
+              w.du[j] = static_cast<uint32_t>(sv) == L + 1 ? kSsspInf : static_cast<uint32_t>(sv >> 32);
+            } else {
+              w.du[j] = kSsspInf;
+              bad = true;
+            }
           }
           const uint32_t s = (p > t0 ? p : t0) - t0;
           atomicOr(&w.flag[s >> 5], 1u << (s & 31));
@@ -357,7 +387,9 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
         const uint32_t msk = static_cast<uint32_t>((2ull << (s & 31)) - 1ull);
         const int slot = static_cast<int>(w.wpre[k] + __popc(w.flag[k] & msk)) - 1;
         const uint32_t e = slot >= 0 ? w.base[slot] + s : a.m;
-        if (e < a.m) {
+        if (kSssp && slot >= 0 && w.du[slot] == kSsspInf) {
+          // skipped entry (see staging)
+        } else if (e < a.m) {
           vv[r] = *at<kNarrow>(a.cols, e);
           if (kSssp) {
             du[r] = w.du[slot];
@@ -483,6 +515,353 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
   __syncthreads();
   f.write(a, nxt, static_cast<uint32_t>(merge_base >> 32) + pn, static_cast<uint32_t>(merge_base) + pe);
   add_stats(a, upd, atom);
+}
+
+template <bool kSssp, bool kNarrow, bool kMulti = false>
+__global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
+  const unsigned long long c = level_begin(a, L);
+  if (static_cast<uint32_t>(c) == 0u) return;
+  if (!level_fits<kSssp, kMulti>(a, c)) {
+    if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrNodeCap);
+    return;
+  }
+  expand_level<kSssp, kNarrow, kMulti>(a, L, c);
+}
+
+// ------------------------------------------------ small frontiers (a8) ----
+// Level loop inside ONE workgroup for small frontiers.  High-diameter graphs
+// spend thousands of levels with a few thousand edges each; there a level's
+// cost is its chain of dependent memory round trips, not its bandwidth, and
+// a one-level launch adds several (tile marks, worklist staging, per-XCD
+// filters, the tail reservation, the kernel boundary).  Here the frontier
+// stays in LDS and a level is two round trips: the arcs of the frontier,
+// then one atomic per arc (OR on the visited bitmap / 64-bit min on the
+// packed state) issued together with speculative loads of the target's
+// offsets, so a discovered node is pushed with its first arc and degree
+// (SSSP adds a coherent read of each pushed node's distance).  Slots of the
+// level's edge space map to entries through an LDS bitmask of entry starts
+// with per-word popcount prefixes.  Pushes also go to the global node list
+// of the next worklist, for the case that they outgrow LDS.
+//
+// The kernel runs levels L0, L0+1, ... and returns when a level is empty,
+// after max_levels levels, or when the next level has more than kSmallF
+// entries or kSmallE edges; then it writes that level in the one-level
+// kernels' worklist format (entries, edge prefix, tile marks, tail counter)
+// and the host continues from ctl->levels.  Entry condition (host): level
+// L0 has at most kSmallF entries and kSmallE edges.
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallWaves = kSmallBlock / 64;
+constexpr uint32_t kSmallF = 4000;   // frontier entries held in LDS
+constexpr uint32_t kSmallE = 16384;  // edges of a level run in this kernel
+constexpr uint32_t kSmallW = kSmallE / 32;
+constexpr int kSmallU = 4;           // edge slots per thread issued together
+constexpr int kSmallC = 4;           // entries per thread per scan chunk
+
+template <bool kSssp>
+struct SmallLds {
+  uint32_t s[kSmallF];      // current level: first arc of entry i
+  uint32_t p[kSmallF];      //   exclusive prefix of the entries' degrees
+  uint32_t du[kSssp ? kSmallF : 1];  //   distance of entry i's node
+  int32_t nv[kSmallF];      // pushes of this level: node,
+  int32_t ns[kSmallF];      //   first arc,
+  int32_t nd[kSmallF];      //   out-degree (> 0)
+  uint32_t flag[kSmallW];   // bit e: an entry starts at edge slot e
+  uint32_t wpre[kSmallW];   // set bits in the words before
+  uint32_t wsum[2][kSmallWaves];
+  uint32_t ncount;          // pushes so far this level
+};
+
+// Exclusive block scan of two counters (kSmallBlock threads).  Returns the
+// thread's prefixes; *tn, *te receive the block totals.
+template <bool kSssp>
+__device__ __forceinline__ void small_scan2(SmallLds<kSssp>& sm, uint32_t xn, uint32_t xe,
+                                            uint32_t* pn, uint32_t* pe, uint32_t* tn, uint32_t* te) {
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t in = wave_incl_scan(xn), ie = wave_incl_scan(xe);
+  __syncthreads();  // wsum may still be read by a previous scan
+  if (lane == 63) {
+    sm.wsum[0][wid] = in;
+    sm.wsum[1][wid] = ie;
+  }
+  __syncthreads();
+  uint32_t bn = 0, be = 0, an = 0, ae = 0;
+  for (int k = 0; k < kSmallWaves; ++k) {
+    const uint32_t wn = sm.wsum[0][k], we = sm.wsum[1][k];
+    if (static_cast<uint32_t>(k) < wid) {
+      bn += wn;
+      be += we;
+    }
+    an += wn;
+    ae += we;
+  }
+  *pn = bn + in - xn;
+  *pe = be + ie - xe;
+  *tn = an;
+  *te = ae;
+}
+
+// The `cnt` (> kSmallF) nodes pushed for level L, all with out-arcs, from
+// the global list out.node to the one-level worklist format.  Returns the
+// level's packed tail.
+template <bool kSssp, bool kNarrow>
+__device__ __forceinline__ unsigned long long small_overflow(const KArgs& a, SmallLds<kSssp>& sm,
+                                                             const Frontier& out, uint32_t cnt) {
+  constexpr uint32_t T = TileCfg<kSssp>::kEdges;
+  constexpr int kPay = kSssp ? 1 : 0;
+  uint32_t base_e = 0;
+  for (uint32_t c0 = 0; c0 < cnt; c0 += kSmallBlock * kSmallC) {
+    int32_t v[kSmallC], st[kSmallC], dg[kSmallC];
+    uint32_t xe = 0;
+#pragma unroll
+    for (int r = 0; r < kSmallC; ++r) {
+      const uint32_t i = c0 + threadIdx.x * kSmallC + r;
+      v[r] = i < cnt ? *at<kNarrow>(out.node, i) : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < kSmallC; ++r) {
+      st[r] = 0;
+      dg[r] = 0;
+      if (v[r] >= 0) {
+        st[r] = *at<kNarrow>(a.offsets, v[r]);
+        dg[r] = *at<kNarrow>(a.offsets, v[r] + 1) - st[r];
+        xe += static_cast<uint32_t>(dg[r]);
+      }
+    }
+    uint32_t pn, pe, tn, te;
+    small_scan2(sm, 0u, xe, &pn, &pe, &tn, &te);
+#pragma unroll
+    for (int r = 0; r < kSmallC; ++r) {
+      if (v[r] >= 0) {
+        write_entry<kPay, T, kNarrow>(a, out, c0 + threadIdx.x * kSmallC + r, base_e + pe, v[r], 0,
+                                      st[r], dg[r]);
+        pe += static_cast<uint32_t>(dg[r]);
+      }
+    }
+    base_e += te;
+  }
+  return (static_cast<unsigned long long>(cnt) << 32) | base_e;
+}
+
+template <bool kSssp, bool kNarrow>
+__global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t L0, uint32_t max_levels) {
+  constexpr uint32_t T = TileCfg<kSssp>::kEdges;
+  constexpr int kPay = kSssp ? 1 : 0;
+  __shared__ SmallLds<kSssp> sm;
+  __shared__ uint32_t red[2][kSmallWaves];
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+
+  // Level L0 from the one-level worklist format.
+  unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L0 % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t nf = static_cast<uint32_t>(c >> 32), E = static_cast<uint32_t>(c);
+  if (E == 0u || nf == 0u || nf > kSmallF || E > kSmallE) return;  // the host checked; uniform
+  {
+    const Frontier f0 = a.fr[L0 & 1];
+    for (uint32_t i = tid; i < nf; i += kSmallBlock) {
+      sm.s[i] = static_cast<uint32_t>(*at<kNarrow>(f0.estart, i));
+      sm.p[i] = *at<kNarrow>(f0.eprefix, i);
+      if (kSssp) {
+        const int32_t u = *at<kNarrow>(f0.node, i);
+        sm.du[i] = static_cast<uint32_t>(__hip_atomic_load(at<kNarrow>(a.dstate, static_cast<uint32_t>(u)),
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
+      }
+    }
+  }
+  uint32_t upd = 0, atom = 0;
+  unsigned long long tot_f = 0, tot_e = 0;  // this launch's levels (thread 0)
+  bool bad = false;
+  uint32_t L = L0;
+  for (;; ++L) {
+    if (tid == 0) {
+      tot_f += nf;
+      tot_e += E;
+      sm.ncount = 0u;
+    }
+    // Entry starts -> bitmask -> per-word prefixes.
+    const uint32_t words = (E + 31) / 32;
+    for (uint32_t k = tid; k < words; k += kSmallBlock) sm.flag[k] = 0u;
+    __syncthreads();
+    for (uint32_t i = tid; i < nf; i += kSmallBlock) atomicOr(&sm.flag[sm.p[i] >> 5], 1u << (sm.p[i] & 31));
+    __syncthreads();
+    if (tid < 64) {
+      constexpr uint32_t kPer = kSmallW / 64;
+      uint32_t x[kPer], t = 0;
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t k = tid * kPer + r;
+        x[r] = k < words ? __popc(sm.flag[k]) : 0u;
+        t += x[r];
+      }
+      uint32_t pre = wave_incl_scan(t) - t;
+#pragma unroll
+      for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t k = tid * kPer + r;
+        if (k < words) sm.wpre[k] = pre;
+        pre += x[r];
+      }
+    }
+    __syncthreads();
+
+    const Frontier nxt = a.fr[(L + 1) & 1];
+    for (uint32_t b0 = 0; b0 < E; b0 += kSmallBlock * kSmallU) {
+      int32_t vv[kSmallU];
+      uint32_t ww[kSmallU], du[kSmallU];
+#pragma unroll
+      for (int r = 0; r < kSmallU; ++r) {
+        const uint32_t e = b0 + r * kSmallBlock + tid;
+        vv[r] = -1;
+        ww[r] = 0;
+        du[r] = 0;
+        if (e < E) {
+          const uint32_t k = e >> 5;
+          const uint32_t msk = static_cast<uint32_t>((2ull << (e & 31)) - 1ull);
+          const uint32_t i = sm.wpre[k] + __popc(sm.flag[k] & msk) - 1;  // entry 0 starts at slot 0
+          const uint32_t arc = sm.s[i] + (e - sm.p[i]);
+          if (i < nf && arc < a.m) {
+            vv[r] = *at<kNarrow>(a.cols, arc);
+            if (kSssp) {
+              ww[r] = *at<kNarrow>(a.weights, arc);
+              du[r] = sm.du[i];
+            }
+          } else {
+            bad = true;
+          }
+        }
+      }
+      // One atomic per arc, with the target's offsets read alongside (the
+      // loads are issued first so they are in flight with the atomics).
+      bool win[kSmallU];
+      int32_t s0[kSmallU], s1[kSmallU];
+#pragma unroll
+      for (int r = 0; r < kSmallU; ++r) {
+        if (vv[r] >= 0 && static_cast<uint32_t>(vv[r]) >= a.n) {
+          bad = true;
+          vv[r] = -1;
+        }
+        s0[r] = 0;
+        s1[r] = 0;
+        if (vv[r] >= 0) {
+          s0[r] = *at<kNarrow>(a.offsets, vv[r]);
+          s1[r] = *at<kNarrow>(a.offsets, vv[r] + 1);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kSmallU; ++r) {
+        win[r] = false;
+        if (vv[r] < 0) continue;
+        ++atom;
+        if (!kSssp) {
+          const uint32_t bit = 1u << (vv[r] & 31);
+          const uint32_t old = atomicOr(at<kNarrow>(a.visited, static_cast<uint32_t>(vv[r]) >> 5), bit);
+          win[r] = !(old & bit);
+        } else {
+          const uint32_t alt = du[r] + ww[r];
+          const unsigned long long old =
+              atomicMin(at<kNarrow>(a.dstate, static_cast<uint32_t>(vv[r])),
+                        (static_cast<unsigned long long>(alt) << 32) | (L + 1));
+          if (alt < static_cast<uint32_t>(old >> 32)) {
+            *at<kNarrow>(a.dist, vv[r]) = alt;  // filter copy for one-level launches
+            ++upd;
+            win[r] = static_cast<uint32_t>(old) != L + 1;  // not yet queued this level
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kSmallU; ++r) {
+        if (!kSssp && win[r]) {
+          *at<kNarrow>(a.levels, vv[r]) = static_cast<int32_t>(L + 1);
+          ++upd;
+        }
+        const int32_t d = s1[r] - s0[r];
+        if (win[r] && d > 0) {  // a node without out-arcs has nothing to expand
+          const uint32_t k = atomicAdd(&sm.ncount, 1u);  // LDS
+          if (k < kSmallF) {
+            sm.nv[k] = vv[r];
+            sm.ns[k] = s0[r];
+            sm.nd[k] = d;
+          }
+          if (k < a.node_cap) *at<kNarrow>(nxt.node, k) = vv[r];
+          else bad = true;
+        }
+      }
+    }
+    if (__any(bad) && lane == 0) atomicOr(&a.ctl->error, kErrBadArc);
+    __syncthreads();
+    // at most one push per node per level, so never above node_cap
+    const uint32_t cnt = min(sm.ncount, a.node_cap);
+    const uint32_t Ln = L + 1;
+    bool stop = false;
+    if (cnt == 0u) {
+      c = 0ull;
+      stop = true;
+    } else if (cnt > kSmallF) {
+      c = small_overflow<kSssp, kNarrow>(a, sm, nxt, cnt);
+      stop = true;
+    } else {
+      // pushes -> the next level's entries: scan the degrees
+      uint32_t d[kSmallC], xe = 0;
+#pragma unroll
+      for (int r = 0; r < kSmallC; ++r) {
+        const uint32_t i = tid * kSmallC + r;
+        d[r] = i < cnt ? static_cast<uint32_t>(sm.nd[i]) : 0u;
+        xe += d[r];
+      }
+      uint32_t pn, pe, tn, te;
+      small_scan2(sm, 0u, xe, &pn, &pe, &tn, &te);
+#pragma unroll
+      for (int r = 0; r < kSmallC; ++r) {
+        const uint32_t i = tid * kSmallC + r;
+        if (i < cnt) {
+          sm.s[i] = static_cast<uint32_t>(sm.ns[i]);
+          sm.p[i] = pe;
+          if (kSssp)
+            sm.du[i] = static_cast<uint32_t>(__hip_atomic_load(at<kNarrow>(a.dstate, static_cast<uint32_t>(sm.nv[i])),
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32);
+          pe += d[r];
+        }
+      }
+      nf = cnt;
+      E = te;
+      c = (static_cast<unsigned long long>(nf) << 32) | E;
+      if (E > kSmallE || Ln - L0 >= max_levels) {
+        __syncthreads();
+        for (uint32_t i = tid; i < nf; i += kSmallBlock)
+          write_entry<kPay, T, kNarrow>(a, nxt, i, sm.p[i], sm.nv[i], 0, sm.ns[i], sm.nd[i]);
+        stop = true;
+      }
+    }
+    if (stop) break;
+    __syncthreads();
+  }
+  // Bookkeeping of every level run here, then the tail of level L + 1 (the
+  // next to expand) and a cleared counter for the level after it.
+  if (tid == 0) {
+    const uint32_t Ln = L + 1;
+    a.ctl->levels = Ln;
+    a.ctl->frontier_entries += tot_f;
+    a.ctl->edges_scanned += tot_e;
+    a.ctl->p_frontier_entries += tot_f;
+    a.ctl->p_edges_scanned += tot_e;
+    __hip_atomic_store(&a.ctl->ctr[Ln % 3], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.ctl->ctr[(Ln + 1) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (a.count_stats) {
+    const uint32_t su = wave_sum(upd), sa = wave_sum(atom);
+    if (lane == 0) {
+      red[0][tid >> 6] = su;
+      red[1][tid >> 6] = sa;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long tu = 0, ta = 0;
+      for (int w = 0; w < kSmallWaves; ++w) {
+        tu += red[0][w];
+        ta += red[1][w];
+      }
+      const int x = blockIdx.x % kXcds;
+      atomicAdd(&a.ctl->xstat[x][2], tu);
+      atomicAdd(&a.ctl->xstat[x][3], ta);
+    }
+  }
 }
 
 // ---------------------------------------------------------- node (BS) ----

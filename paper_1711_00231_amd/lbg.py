@@ -364,9 +364,12 @@ def profile_enable(enable: bool = True, reset: bool = True) -> None:
 
 
 def profile_read(which) -> dict:
-    """Expansion-kernel totals since the last reset: which = "bfs", "sssp" or
-    "batch" (booleans select sssp/bfs)."""
-    idx = {"bfs": 0, "sssp": 1, "batch": 2}.get(which, None) if isinstance(which, str) else int(bool(which))
+    """Expansion-kernel totals since the last reset: which = "bfs", "sssp",
+    "batch" (one-level launches), "bfs_small" or "sssp_small" (launches of
+    the single-workgroup small-frontier level loop); booleans select
+    sssp/bfs."""
+    idx = ({"bfs": 0, "sssp": 1, "batch": 2, "bfs_small": 3, "sssp_small": 4}[which]
+           if isinstance(which, str) else int(bool(which)))
     p = Profile()
     lib.lbg_profile_read(idx, ctypes.byref(p))
     return p.as_dict()

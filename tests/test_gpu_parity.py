@@ -110,6 +110,52 @@ def test_grid_small(strat):
     _check(h, _dev(h), [0], strat)
 
 
+def _barbell(path_len, n_mid, k_mid, salt):
+    """A path, a dense uniform block, another path (all arcs both ways): the
+    frontier is tiny for path_len levels, explodes inside the block, then is
+    tiny again, so a solve switches between the small-frontier kernel and
+    one-level launches and back."""
+    blk = graphgen.uniform(n=n_mid, k=k_mid, wlo=1, whi=9, salt=salt)
+    P = path_len
+    n = 2 * P + n_mid
+    src = [np.arange(P - 1), P + np.repeat(np.arange(n_mid), blk.degrees), P + n_mid + np.arange(P - 1),
+           np.array([P - 1, P + n_mid - 1])]
+    dst = [np.arange(1, P), P + blk.cols.astype(np.int64), P + n_mid + np.arange(1, P),
+           np.array([P, P + n_mid])]
+    w = [np.full(P - 1, 3), blk.weights.astype(np.int64), np.full(P - 1, 5), np.array([2, 4])]
+    s_all, d_all, w_all = np.concatenate(src), np.concatenate(dst), np.concatenate(w)
+    return graphgen.from_edges(n, np.concatenate([s_all, d_all]), np.concatenate([d_all, s_all]),
+                               np.concatenate([w_all, w_all]), "barbell")
+
+
+def test_small_frontier_switching():
+    """Balanced solves run small levels in the single-workgroup kernel and
+    large ones as one-level launches; results and work counters must not
+    depend on where the switches fall."""
+    g = _barbell(400, 20000, 48, salt=5)
+    dg = _dev(g)
+    exp_l = O.bfs(g.offsets, g.cols, 0)
+    exp_d = O.dijkstra(g.offsets, g.cols, g.weights, 0)
+    reached = exp_l != pins.BFS_INF
+    lbg.profile_enable(True, reset=True)
+    lv, st = _gpu_bfs(dg, 0, "balanced", stats=True)
+    d, st_d = _gpu_sssp(dg, 0, "balanced", stats=True)
+    lbg.profile_enable(False, reset=False)
+    assert np.array_equal(lv, exp_l)
+    assert np.array_equal(d, exp_d)
+    one, small = lbg.profile_read("bfs"), lbg.profile_read("bfs_small")
+    assert st["levels"] == int(exp_l[reached].max()) + 1
+    assert one["frontier_entries"] + small["frontier_entries"] == st["frontier_entries"]
+    assert one["edges_scanned"] + small["edges_scanned"] == st["edges_scanned"] == g.reached_arcs(reached)
+    assert one["updates"] + small["updates"] == st["updates"] == int(reached.sum()) - 1
+    # path, block, path: small -> one-level -> small at least
+    assert small["launches"] >= 2 and one["launches"] >= 1
+    assert lbg.profile_read("sssp_small")["launches"] >= 2
+    # a chain long enough that almost every level runs on the device
+    h = pins.path_graph(5000, np.arange(1, 5000) % 7)
+    _check(h, _dev(h), [0, 2500], "balanced")
+
+
 def test_repeat_runs_identical():
     """Relaxation order differs from run to run; results must not."""
     g = graphgen.rmat(14)
