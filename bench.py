@@ -83,6 +83,29 @@ def make_workload(name):
     return g, srcs, desc, sym
 
 
+def recorded_traffic():
+    """HBM-side bytes per launch of the expansion kernels, from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary; empty when the kernel sources
+    have changed since those counters were taken."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("paper_1711_00231_amd/csrc/lbg_kernels.hpp", "paper_1711_00231_amd/csrc/lbg_device.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    out = {}
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.txt")):
+        lines = open(path).read().splitlines()
+        if f"kernel_sources_sha256: {h.hexdigest()}" not in lines:
+            continue
+        for ln in lines:
+            if ln.startswith("traffic_per_launch "):
+                name, val = ln[len("traffic_per_launch "):].rsplit(":", 1)
+                out[name.strip()] = float(val)
+    return out
+
+
 def algorithmic_bytes(kind, prof):
     if kind == "bfs":
         return 8 * prof["edges_scanned"] + 20 * prof["updates"]
@@ -210,11 +233,14 @@ def run_plain(args, lbg, torch, dev):
                           "launches": nl, "kernel_ms": p["kernel_ms"] + p["empty_ms"],
                           "bytes": algorithmic_bytes(kind, p)}
         dom = max(kern, key=lambda k: kern[k]["kernel_ms"])
+        traffic = recorded_traffic() if args.workload == "rmat22" else {}
         for kind, kd in kern.items():
             achieved = kd["bytes"] / (kd["kernel_ms"] / 1e3) / 1e9
+            t = traffic.get(kd["kernel"])
             obj = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                   "traffic": None, "kernel": kd["kernel"], "launches": kd["launches"],
+                   "traffic": round(t) if t is not None else None,
+                   "kernel": kd["kernel"], "launches": kd["launches"],
                    "avg_launch_us": round(kd["kernel_ms"] * 1e3 / max(kd["launches"], 1), 3),
                    "bytes_per_launch": round(kd["bytes"] / max(kd["launches"], 1))}
             out["roofline" if kind == dom else "roofline_" + kind] = obj
