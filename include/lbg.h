@@ -158,9 +158,10 @@ void lbg_profile_read(int32_t which, lbg_profile* out);
  *
  * The graph is a disjoint union of instances in one CSR with global node
  * ids: instance k owns the node range [lo, hi) and every arc leaving a node
- * of that range lands in it (pack instances by offsetting their ids).  A BFS
- * query is computed as a unit-weight relaxation (the same least fixed point),
- * so BFS and SSSP queries mix freely in one batch.
+ * of that range lands in it (pack instances by offsetting their ids).  BFS
+ * and SSSP queries mix freely in one batch: a BFS query claims each node of
+ * its row once, with a bit in a per-row bitmap, and an SSSP query relaxes
+ * with the atomic minimum of the single-query path.
  * ------------------------------------------------------------------------ */
 #define LBG_KIND_BFS 0
 #define LBG_KIND_SSSP 1

@@ -436,9 +436,17 @@ int solve(const Problem& P) {
 }
 
 
+// 2-D grid of the row fill/finish kernels: y over the queries, x over the
+// kRowChunk chunks of the longest row.
+dim3 row_grid(int64_t queries, int64_t max_len) {
+  const int64_t chunks = (max_len + lbg::kRowChunk - 1) / lbg::kRowChunk;
+  return dim3(static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(chunks, 256))),
+              static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(queries, 65535))));
+}
+
 // ----------------------------------------------------------------- batch --
 struct BatchLayout {
-  size_t ctl, qtab, dstate, node[2], qid[2], eprefix[2], estart[2], tile[2], total;
+  size_t ctl, qtab, dstate, rbits, node[2], qid[2], eprefix[2], estart[2], tile[2], total;
   uint32_t node_cap, tile_cap;
 };
 
@@ -453,6 +461,7 @@ BatchLayout batch_layout(int32_t num_queries, int64_t rows, int64_t total_arcs) 
   L.ctl = take(sizeof(Ctl));
   L.qtab = take(sizeof(lbg::QInfo) * static_cast<size_t>(num_queries));
   L.dstate = take(sizeof(unsigned long long) * static_cast<size_t>(rows));
+  L.rbits = take(sizeof(uint32_t) * ((static_cast<size_t>(rows) + 31) / 32));  // BFS rows
   L.node_cap = static_cast<uint32_t>(rows);
   L.tile_cap = static_cast<uint32_t>((total_arcs + lbg::kMultiTile - 1) / lbg::kMultiTile + 2);
   for (int b = 0; b < 2; ++b) {
@@ -500,7 +509,8 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
     I.delta = I.row_start - Q.lo;
     I.kind = Q.kind;
     I.src = Q.src;
-    I.pad[0] = I.pad[1] = I.pad[2] = 0;
+    I.level0 = 0;
+    I.pad[0] = I.pad[1] = 0;
   }
 
   char* ws = static_cast<char*>(workspace);
@@ -510,6 +520,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
   a.weights = weights;
   a.dist = out;
   a.dstate = reinterpret_cast<unsigned long long*>(ws + Lay.dstate);
+  a.visited = reinterpret_cast<uint32_t*>(ws + Lay.rbits);
   for (int b = 0; b < 2; ++b) {
     a.fr[b].node = reinterpret_cast<int32_t*>(ws + Lay.node[b]);
     a.fr[b].qid = reinterpret_cast<int32_t*>(ws + Lay.qid[b]);
@@ -538,10 +549,11 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
                          hipMemcpyHostToDevice, st));
   const bool narrow = n < (1 << 29) && m < (int64_t{1} << 30) && rows < (int64_t{1} << 29);
   const Grids& GR = grids();
-  const int fill_blocks = std::min(num_queries, 4096);
+  int64_t max_len = 1;
+  for (const lbg::QInfo& I : qt) max_len = std::max<int64_t>(max_len, I.row_len);
+  const dim3 rgrid = row_grid(num_queries, max_len);
   const int seed_blocks = (num_queries + lbg::kBlock - 1) / lbg::kBlock;
-  const int fin_blocks = std::min(num_queries, 4096);
-  hipLaunchKernelGGL(lbg::k_batch_fill, dim3(fill_blocks), dim3(lbg::kBlock), 0, st, a);
+  hipLaunchKernelGGL(lbg::k_batch_fill, rgrid, dim3(lbg::kBlock), 0, st, a);
   if (narrow) hipLaunchKernelGGL(lbg::k_batch_seed<true>, dim3(seed_blocks), dim3(lbg::kBlock), 0, st, a);
   else hipLaunchKernelGGL(lbg::k_batch_seed<false>, dim3(seed_blocks), dim3(lbg::kBlock), 0, st, a);
   HIP_TRY(hipGetLastError());
@@ -567,7 +579,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
         HIP_TRY(hipEventRecord(e, st));
       }
     }
-    hipLaunchKernelGGL(lbg::k_batch_finish, dim3(fin_blocks), dim3(lbg::kBlock), 0, st, a, L);
+    hipLaunchKernelGGL(lbg::k_batch_finish, rgrid, dim3(lbg::kBlock), 0, st, a, L);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -611,7 +623,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
 // ---------------------------------------------------------------- engine --
 struct EngineLayout {
   BatchLayout b;
-  size_t qlast, slots, total;
+  size_t qlast, slots, qstage, total;
 };
 
 EngineLayout engine_layout(int32_t max_queries, int64_t max_rows, int64_t max_level_arcs) {
@@ -622,6 +634,8 @@ EngineLayout engine_layout(int32_t max_queries, int64_t max_rows, int64_t max_le
   off += align_up(sizeof(uint32_t) * static_cast<size_t>(max_queries));
   E.slots = off;
   off += align_up(sizeof(int32_t) * static_cast<size_t>(max_queries));
+  E.qstage = off;  // descriptors of the queries being admitted
+  off += align_up(sizeof(lbg::QInfo) * static_cast<size_t>(max_queries));
   E.total = off;
   return E;
 }
@@ -642,6 +656,7 @@ struct lbg_engine {
   std::vector<int32_t> pending, done;
   uint32_t* host_qlast = nullptr;  // pinned
   int32_t* host_slots = nullptr;   // pinned
+  lbg::QInfo* host_qstage = nullptr;  // pinned
   Ctl* host_ctl = nullptr;         // pinned
   int64_t steps = 0;
 };
@@ -697,18 +712,20 @@ int lbg_engine_create(const int32_t* offsets, const int32_t* cols, const uint32_
   void* p1 = nullptr;
   void* p2 = nullptr;
   void* p3 = nullptr;
+  void* p4 = nullptr;
   if (hipHostMalloc(&p1, sizeof(uint32_t) * max_queries, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&p2, sizeof(int32_t) * max_queries, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(&p3, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
-    if (p1) (void)hipHostFree(p1);
-    if (p2) (void)hipHostFree(p2);
-    if (p3) (void)hipHostFree(p3);
+      hipHostMalloc(&p3, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(&p4, sizeof(lbg::QInfo) * max_queries, hipHostMallocDefault) != hipSuccess) {
+    for (void* p : {p1, p2, p3, p4})
+      if (p) (void)hipHostFree(p);
     delete e;
     return fail(LBG_EHIP, "hipHostMalloc failed");
   }
   e->host_qlast = static_cast<uint32_t*>(p1);
   e->host_slots = static_cast<int32_t*>(p2);
   e->host_ctl = static_cast<Ctl*>(p3);
+  e->host_qstage = static_cast<lbg::QInfo*>(p4);
   const BatchLayout& Lay = e->lay.b;
   KArgs& a = e->a;
   a.offsets = offsets;
@@ -716,6 +733,7 @@ int lbg_engine_create(const int32_t* offsets, const int32_t* cols, const uint32_
   a.weights = weights;
   a.dist = rows_out;
   a.dstate = reinterpret_cast<unsigned long long*>(e->ws + Lay.dstate);
+  a.visited = reinterpret_cast<uint32_t*>(e->ws + Lay.rbits);
   for (int b = 0; b < 2; ++b) {
     a.fr[b].node = reinterpret_cast<int32_t*>(e->ws + Lay.node[b]);
     a.fr[b].qid = reinterpret_cast<int32_t*>(e->ws + Lay.qid[b]);
@@ -766,7 +784,8 @@ int lbg_engine_submit(lbg_engine* e, const lbg_query* q, int32_t* slot) {
   I.delta = I.row_start - q->lo;
   I.kind = q->kind;
   I.src = q->src;
-  I.pad[0] = I.pad[1] = I.pad[2] = 0;
+  I.level0 = 0;
+  I.pad[0] = I.pad[1] = 0;
   e->state[static_cast<size_t>(s)] = 1;
   e->pending.push_back(s);
   *slot = s;
@@ -779,17 +798,24 @@ int lbg_engine_step(lbg_engine* e, int32_t levels, int32_t* finished) {
   const hipStream_t st = e->st;
   const Grids& GR = grids();
   if (!e->pending.empty()) {
+    // Admissions: descriptors and slots go up in one copy each (pinned
+    // staging; the previous step's copies finished before it returned).
     const int cnt = static_cast<int>(e->pending.size());
     for (int k = 0; k < cnt; ++k) {
       const int32_t s = e->pending[static_cast<size_t>(k)];
       e->host_slots[k] = s;
-      HIP_TRY(hipMemcpyAsync(e->ws + e->lay.b.qtab + sizeof(lbg::QInfo) * s, &e->qt[static_cast<size_t>(s)],
-                             sizeof(lbg::QInfo), hipMemcpyHostToDevice, st));
+      e->qt[static_cast<size_t>(s)].level0 = e->L;  // its source joins worklist L
+      e->host_qstage[k] = e->qt[static_cast<size_t>(s)];
     }
     int32_t* dslots = reinterpret_cast<int32_t*>(e->ws + e->lay.slots);
+    lbg::QInfo* dstage = reinterpret_cast<lbg::QInfo*>(e->ws + e->lay.qstage);
+    HIP_TRY(hipMemcpyAsync(dstage, e->host_qstage, sizeof(lbg::QInfo) * cnt, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(dslots, e->host_slots, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(lbg::k_engine_fill, dim3(std::min(cnt, 4096)), dim3(lbg::kBlock), 0, st, a,
-                       static_cast<const int32_t*>(dslots), cnt);
+    int64_t max_len = 1;
+    for (int k = 0; k < cnt; ++k) max_len = std::max<int64_t>(max_len, e->host_qstage[k].row_len);
+    hipLaunchKernelGGL(lbg::k_engine_fill, row_grid(cnt, max_len), dim3(lbg::kBlock), 0, st, a,
+                       static_cast<const int32_t*>(dslots), static_cast<const lbg::QInfo*>(dstage),
+                       reinterpret_cast<lbg::QInfo*>(e->ws + e->lay.b.qtab), cnt);
     const int sb = (cnt + lbg::kBlock - 1) / lbg::kBlock;
     if (e->narrow) hipLaunchKernelGGL(lbg::k_engine_seed<true>, dim3(sb), dim3(lbg::kBlock), 0, st, a, static_cast<const int32_t*>(dslots), cnt, e->L);
     else hipLaunchKernelGGL(lbg::k_engine_seed<false>, dim3(sb), dim3(lbg::kBlock), 0, st, a, static_cast<const int32_t*>(dslots), cnt, e->L);
@@ -817,7 +843,9 @@ int lbg_engine_step(lbg_engine* e, int32_t levels, int32_t* finished) {
   if (cnt) {
     int32_t* dslots = reinterpret_cast<int32_t*>(e->ws + e->lay.slots);
     HIP_TRY(hipMemcpyAsync(dslots, e->host_slots, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(lbg::k_engine_finish, dim3(std::min(cnt, 4096)), dim3(lbg::kBlock), 0, st, a,
+    int64_t max_len = 1;
+    for (int32_t s : e->done) max_len = std::max<int64_t>(max_len, e->qt[static_cast<size_t>(s)].row_len);
+    hipLaunchKernelGGL(lbg::k_engine_finish, row_grid(cnt, max_len), dim3(lbg::kBlock), 0, st, a,
                        static_cast<const int32_t*>(dslots), cnt);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
@@ -867,6 +895,7 @@ void lbg_engine_destroy(lbg_engine* e) {
   if (e->host_qlast) (void)hipHostFree(e->host_qlast);
   if (e->host_slots) (void)hipHostFree(e->host_slots);
   if (e->host_ctl) (void)hipHostFree(e->host_ctl);
+  if (e->host_qstage) (void)hipHostFree(e->host_qstage);
   delete e;
 }
 

@@ -32,7 +32,8 @@ struct QInfo {
   int32_t row_start;  // first element of the query's result row
   int32_t row_len;    // hi - lo
   int32_t src;        // global source node
-  int32_t pad[3];
+  uint32_t level0;    // level whose worklist received the source (engine admissions)
+  int32_t pad[2];
 };
 constexpr int kXcds = 8;                 // MI355X: 8 XCDs, workgroups dealt round-robin
 

@@ -327,9 +327,11 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
           valid = true;
           w.base[j] = st + t0 - p;  // arc of slot s is base + s (mod 2^32)
           int32_t delta = 0;
+          uint32_t level0 = 0;
           if (kMulti) {
             const QInfo qi = a.qtab[q];
             delta = qi.delta;
+            level0 = qi.level0;
             w.delta[j] = qi.delta;
             w.lo[j] = qi.row_start - qi.delta;
             w.lenkind[j] = static_cast<uint32_t>(qi.row_len) | (qi.kind ? 0x80000000u : 0u);
@@ -337,7 +339,15 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
           }
           if (kSssp) {
             const uint32_t row = static_cast<uint32_t>(node + delta);
-            if (row < state_len) {
+            if (kMulti && !(w.lenkind[j] >> 31)) {
+              // BFS query: its frontier nodes are exactly its nodes at hop
+              // distance L - level0
+              w.du[j] = L - level0;
+              if (row >= state_len) {
+                w.du[j] = kSsspInf;
+                bad = true;
+              }
+            } else if (row < state_len) {
               // A node that already improved during this launch is queued
               // for the next iteration with a distance at least as good, and
               // its arcs are relaxed there: skip them here (du = infinity
@@ -371,6 +381,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
     int32_t dl[kMulti ? kItems : 1];
     int32_t qd[kMulti ? kItems : 1];
     bool inside[kMulti ? kItems : 1];
+    bool bfsq[kMulti ? kItems : 1];  // batched: the slot belongs to a BFS query
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t s = r * 64 + lane;
@@ -381,6 +392,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
         dl[kMulti ? r : 0] = 0;
         qd[kMulti ? r : 0] = 0;
         inside[kMulti ? r : 0] = true;
+        bfsq[kMulti ? r : 0] = false;
       }
       if (t0 + s < t1) {
         const uint32_t k = s >> 5;
@@ -399,6 +411,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
               const uint32_t lk = w.lenkind[slot];
               inside[kMulti ? r : 0] =
                   static_cast<uint32_t>(vv[r] - w.lo[slot]) < (lk & 0x7fffffffu);
+              bfsq[kMulti ? r : 0] = !(lk >> 31);
               ww[r] = (lk >> 31) ? *at<kNarrow>(a.weights, e) : 1u;
             } else {
               ww[r] = *at<kNarrow>(a.weights, e);
@@ -454,17 +467,31 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
     } else {
       // Phase B: filter distances; phase C: one 64-bit atomicMin per
       // improving arc, returning both the old distance and whether the node
-      // is already queued for this iteration.
+      // is already queued for this iteration.  Batched BFS queries instead
+      // read and claim their bit in the per-row bitmap (a BFS node is final
+      // when first reached), and write the level straight to their row.
       uint32_t cd[kItems];
 #pragma unroll
-      for (int r = 0; r < kItems; ++r)
-        cd[r] = vv[r] >= 0 ? *at<kNarrow>(static_cast<const uint32_t*>(a.dist), row[r]) : 0u;
+      for (int r = 0; r < kItems; ++r) {
+        cd[r] = 0u;
+        if (vv[r] >= 0)
+          cd[r] = (kMulti && bfsq[kMulti ? r : 0]) ? *at<kNarrow>(static_cast<const uint32_t*>(a.visited), row[r] >> 5)
+                                                   : *at<kNarrow>(static_cast<const uint32_t*>(a.dist), row[r]);
+      }
       unsigned long long old[kItems];
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t alt = du[r] + ww[r];
         old[r] = 0ull;
-        if (vv[r] >= 0 && alt < cd[r]) {
+        if (kMulti && bfsq[kMulti ? r : 0]) {
+          const uint32_t bit = 1u << (row[r] & 31);
+          if (vv[r] >= 0 && !(cd[r] & bit)) {
+            ++atom;
+            old[r] = atomicOr(at<kNarrow>(a.visited, row[r] >> 5), bit);
+          } else {
+            old[r] = bit;
+          }
+        } else if (vv[r] >= 0 && alt < cd[r]) {
           ++atom;
           old[r] = atomicMin(at<kNarrow>(a.dstate, row[r]),
                              (static_cast<unsigned long long>(alt) << 32) | (L + 1));
@@ -473,10 +500,17 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t alt = du[r] + ww[r];
-        const bool better = vv[r] >= 0 && alt < static_cast<uint32_t>(old[r] >> 32);
-        if (better) *at<kNarrow>(a.dist, row[r]) = alt;  // filter copy (see top of file)
-        upd += better ? 1u : 0u;
-        push[r] = better && static_cast<uint32_t>(old[r]) != L + 1;
+        if (kMulti && bfsq[kMulti ? r : 0]) {
+          const bool won = vv[r] >= 0 && !(static_cast<uint32_t>(old[r]) & (1u << (row[r] & 31)));
+          if (won) *at<kNarrow>(a.dist, row[r]) = alt;  // = L + 1, final
+          upd += won ? 1u : 0u;
+          push[r] = won;
+        } else {
+          const bool better = vv[r] >= 0 && alt < static_cast<uint32_t>(old[r] >> 32);
+          if (better) *at<kNarrow>(a.dist, row[r]) = alt;  // filter copy (see top of file)
+          upd += better ? 1u : 0u;
+          push[r] = better && static_cast<uint32_t>(old[r]) != L + 1;
+        }
       }
     }
     if (__any(bad) && lane == 0) atomicOr(&a.ctl->error, kErrBadArc);
@@ -970,28 +1004,65 @@ __global__ __launch_bounds__(kBlock) void k_expand_edge(KArgs a, uint32_t L) {
   add_stats(a, upd, atom);
 }
 
-// ------------------------------------------------------------- batched --
-// Batched solves: every query owns a row of node state; the queries' rows
-// (and nothing between them) start at infinity and the control block is
-// cleared.
-__global__ __launch_bounds__(kBlock) void k_batch_fill(KArgs a) {
-  const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
-  for (uint32_t q = blockIdx.x; q < a.num_queries; q += gridDim.x) {
-    const QInfo qi = a.qtab[q];
-    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
-      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
-      a.dstate[idx] = static_cast<unsigned long long>(kSsspInf) << 32;
-      a.dist[idx] = kSsspInf;
+// Batched rows.  SSSP rows keep the packed state; BFS rows keep one bit per
+// row in the row bitmap (`visited`) and their level in the output row.  Fill
+// and finish kernels run a 2-D grid: y walks the queries, x the kRowChunk
+// element chunks of a query's row, so a large instance is spread over many
+// workgroups.  Bitmap words that a chunk shares with a neighbouring chunk or
+// row range are cleared with an atomic AND.
+constexpr uint32_t kRowChunk = 4096;
+
+__device__ __forceinline__ void fill_chunk(const KArgs& a, const QInfo& qi, uint32_t c0) {
+  const uint32_t r0 = static_cast<uint32_t>(qi.row_start) + c0;
+  const uint32_t r1 = static_cast<uint32_t>(qi.row_start) + min(static_cast<uint32_t>(qi.row_len), c0 + kRowChunk);
+  for (uint32_t idx = r0 + threadIdx.x; idx < r1; idx += kBlock) {
+    if (qi.kind) a.dstate[idx] = static_cast<unsigned long long>(kSsspInf) << 32;
+    a.dist[idx] = kSsspInf;
+  }
+  if (!qi.kind) {
+    const uint32_t w0 = r0 >> 5, w1 = (r1 - 1) >> 5;
+    for (uint32_t w = w0 + threadIdx.x; w <= w1; w += kBlock) {
+      const uint32_t lo = w == w0 ? (r0 & 31) : 0u;
+      const uint32_t hi = w == w1 ? ((r1 - 1) & 31) : 31u;
+      const uint32_t m = (hi == 31u ? ~0u : ((2u << hi) - 1u)) & ~((1u << lo) - 1u);
+      if (m == ~0u) a.visited[w] = 0u;
+      else atomicAnd(&a.visited[w], ~m);
     }
   }
-  if (gid == 0) {
-    a.ctl->ctr[0] = a.ctl->ctr[1] = a.ctl->ctr[2] = 0ull;
-    a.ctl->error = 0u;
-    a.ctl->levels = 0u;
-    a.ctl->frontier_entries = 0ull;
-    a.ctl->edges_scanned = 0ull;
+}
+
+__device__ __forceinline__ void finish_chunk(const KArgs& a, const QInfo& qi, uint32_t c0) {
+  const uint32_t r0 = static_cast<uint32_t>(qi.row_start) + c0;
+  const uint32_t r1 = static_cast<uint32_t>(qi.row_start) + min(static_cast<uint32_t>(qi.row_len), c0 + kRowChunk);
+  for (uint32_t idx = r0 + threadIdx.x; idx < r1; idx += kBlock) {
+    if (qi.kind) a.dist[idx] = static_cast<uint32_t>(a.dstate[idx] >> 32);
+    else if (a.dist[idx] == kSsspInf) a.dist[idx] = kBfsInf;
   }
-  if (gid < kXcds * 16) a.ctl->xstat[gid / 16][gid % 16] = 0ull;
+}
+
+__device__ __forceinline__ void seed_row(const KArgs& a, const QInfo& qi) {
+  const uint32_t row = static_cast<uint32_t>(qi.src + qi.delta);
+  if (qi.kind) a.dstate[row] = 0ull;
+  else atomicOr(&a.visited[row >> 5], 1u << (row & 31));
+  a.dist[row] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_fill(KArgs a) {
+  for (uint32_t q = blockIdx.y; q < a.num_queries; q += gridDim.y) {
+    const QInfo qi = a.qtab[q];
+    for (uint32_t c0 = blockIdx.x * kRowChunk; c0 < static_cast<uint32_t>(qi.row_len); c0 += gridDim.x * kRowChunk)
+      fill_chunk(a, qi, c0);
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (threadIdx.x == 0) {
+      a.ctl->ctr[0] = a.ctl->ctr[1] = a.ctl->ctr[2] = 0ull;
+      a.ctl->error = 0u;
+      a.ctl->levels = 0u;
+      a.ctl->frontier_entries = 0ull;
+      a.ctl->edges_scanned = 0ull;
+    }
+    for (uint32_t k = threadIdx.x; k < kXcds * 16; k += kBlock) a.ctl->xstat[k / 16][k % 16] = 0ull;
+  }
 }
 
 // Each query's source gets distance 0 and (query, source) enters worklist 0.
@@ -1003,9 +1074,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_seed(KArgs a) {
   if (act) {
     const QInfo qi = a.qtab[q];
     v = qi.src;
-    const uint32_t row = static_cast<uint32_t>(v + qi.delta);
-    a.dstate[row] = 0ull;
-    a.dist[row] = 0u;
+    seed_row(a, qi);
   }
   Frontier f0 = a.fr[0];
   f0.level = 0;
@@ -1015,14 +1084,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_seed(KArgs a) {
 // ------------------------------------------------------------------ engine --
 // Continuous batching: queries join a running batch between levels.  Rows of
 // the listed slots start at infinity ...
-__global__ __launch_bounds__(kBlock) void k_engine_fill(KArgs a, const int32_t* slots, int count) {
-  for (int k = blockIdx.x; k < count; k += gridDim.x) {
-    const QInfo qi = a.qtab[slots[k]];
-    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
-      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
-      a.dstate[idx] = static_cast<unsigned long long>(kSsspInf) << 32;
-      a.dist[idx] = kSsspInf;
-    }
+__global__ __launch_bounds__(kBlock) void k_engine_fill(KArgs a, const int32_t* slots, const QInfo* stage,
+                                                        QInfo* qtab, int count) {
+  for (int k = blockIdx.y; k < count; k += gridDim.y) {
+    const QInfo qi = stage[k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) qtab[slots[k]] = qi;  // read there by later kernels
+    for (uint32_t c0 = blockIdx.x * kRowChunk; c0 < static_cast<uint32_t>(qi.row_len); c0 += gridDim.x * kRowChunk)
+      fill_chunk(a, qi, c0);
   }
 }
 
@@ -1038,9 +1106,7 @@ __global__ __launch_bounds__(kBlock) void k_engine_seed(KArgs a, const int32_t* 
     q = slots[k];
     const QInfo qi = a.qtab[q];
     v = qi.src;
-    const uint32_t row = static_cast<uint32_t>(v + qi.delta);
-    a.dstate[row] = 0ull;
-    a.dist[row] = 0u;
+    seed_row(a, qi);
     a.qlast[q] = L;  // even a source without out-arcs is live until level L ends
   }
   Frontier f = a.fr[L & 1];
@@ -1050,13 +1116,10 @@ __global__ __launch_bounds__(kBlock) void k_engine_seed(KArgs a, const int32_t* 
 
 // Rows of finished slots are written out (as k_batch_finish).
 __global__ __launch_bounds__(kBlock) void k_engine_finish(KArgs a, const int32_t* slots, int count) {
-  for (int k = blockIdx.x; k < count; k += gridDim.x) {
+  for (int k = blockIdx.y; k < count; k += gridDim.y) {
     const QInfo qi = a.qtab[slots[k]];
-    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
-      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
-      const uint32_t d = static_cast<uint32_t>(a.dstate[idx] >> 32);
-      a.dist[idx] = (qi.kind || d != kSsspInf) ? d : kBfsInf;
-    }
+    for (uint32_t c0 = blockIdx.x * kRowChunk; c0 < static_cast<uint32_t>(qi.row_len); c0 += gridDim.x * kRowChunk)
+      finish_chunk(a, qi, c0);
   }
 }
 
@@ -1066,13 +1129,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(KArgs a, uint32_t L) {
   const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
   if (static_cast<uint32_t>(c) != 0u) return;
-  for (uint32_t q = blockIdx.x; q < a.num_queries; q += gridDim.x) {
+  for (uint32_t q = blockIdx.y; q < a.num_queries; q += gridDim.y) {
     const QInfo qi = a.qtab[q];
-    for (int32_t r = threadIdx.x; r < qi.row_len; r += kBlock) {
-      const uint32_t idx = static_cast<uint32_t>(qi.row_start + r);
-      const uint32_t d = static_cast<uint32_t>(a.dstate[idx] >> 32);
-      a.dist[idx] = (qi.kind || d != kSsspInf) ? d : kBfsInf;
-    }
+    for (uint32_t c0 = blockIdx.x * kRowChunk; c0 < static_cast<uint32_t>(qi.row_len); c0 += gridDim.x * kRowChunk)
+      finish_chunk(a, qi, c0);
   }
 }
 
