@@ -323,29 +323,36 @@ def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
 
 
 # -------------------------------------------------------------- serving --
-def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_count=8):
+def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_count=8,
+              big_arcs=1 << 23):
     import graphgen
     from paper_1711_00231_amd import serve
 
     t0 = time.perf_counter()
     resident = [graphgen.rmat(s, salt=50 + s) for s in scales]
+    names = [f"rmat{s}" for s in scales]
     uploads = [graphgen.uniform(n=int(2 ** e), k=8, wlo=1, whi=255, salt=60 + i)
                for i, e in enumerate(np.linspace(12, 16, upload_count))]
-    u, nb, eb = graphgen.pack(resident)
+    # every resident instance stays in HBM as its own CSR (plain solves);
+    # the small ones are also packed, with the upload regions, for the engine
+    singles = {nm: lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
+               for nm, g in zip(names, resident)}
+    small = [(nm, g) for nm, g in zip(names, resident) if g.m < big_arcs]
+    u, nb, eb = graphgen.pack([g for _, g in small])
     NC, MC, R = (1 << 16) + 1, (1 << 16) * 8, 8
     off_e, cols_e, w_e = serve.UploadArena.empty_arrays(R, NC, MC, u.n, u.m)
     off = np.concatenate([u.offsets[:-1].astype(np.int64), off_e, [u.m + R * MC]])
     dg = lbg.DeviceGraph.from_numpy(off, np.concatenate([u.cols, cols_e]),
                                     np.concatenate([u.weights, w_e]), device=dev)
     del off, off_e, cols_e, w_e
-    log(f"serve: resident scales {scales}, n={u.n} m={u.m} built in {time.perf_counter() - t0:.1f}s")
-    inst = {f"rmat{s}": serve.Instance(int(nb[i]), int(nb[i + 1]), int(eb[i + 1] - eb[i]))
-            for i, s in enumerate(scales)}
-    srcs = {f"rmat{s}": graphgen.sources(g, 64, graphgen.FAMILY_SERVE, salt=s)
-            for s, g in zip(scales, resident)}
+    log(f"serve: resident scales {scales} ({len(small)} batched), packed n={u.n} m={u.m} "
+        f"built in {time.perf_counter() - t0:.1f}s")
+    inst = {nm: serve.Instance(0, g.n, g.m) for nm, g in zip(names, resident)}
+    for i, (nm, g) in enumerate(small):
+        inst[nm] = serve.Instance(int(nb[i]), int(nb[i + 1]), int(eb[i + 1] - eb[i]))
+    srcs = {nm: graphgen.sources(g, 64, graphgen.FAMILY_SERVE, salt=s)
+            for nm, s, g in zip(names, scales, resident)}
     # saturation of plain per-query launches: mean service time of the mix
-    singles = {f"rmat{s}": lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
-               for s, g in zip(scales, resident)}
     up_dev = {id(g): lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
               for g in uploads}
     ws1 = lbg.Workspace(dev)
@@ -362,20 +369,42 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t)
     sat = 1.0 / float(np.mean(svc))
-    del singles, up_dev, ws1
-    max_rows = 6 * max(g.n for g in resident) + 16 * NC
+    max_rows = 6 * max([g.n for _, g in small] + [1]) + 16 * NC
     eng = lbg.Engine(dg, max_queries=64, max_rows=max_rows,
                      max_level_arcs=min(2**32 - 1, 8 * (u.m + R * MC)))
+    big = {nm: singles[nm] for nm, g in zip(names, resident) if g.m >= big_arcs}
+    lane = serve.gpu_plain_lane(big, big_arcs) if big else None
+
+    def plain_serve(reqs):
+        """The same arrivals served FCFS by one plain call per request (upload
+        graphs already resident: no copy is charged to the plain path)."""
+        t0 = time.perf_counter()
+        lat = []
+        for r in reqs:
+            while time.perf_counter() - t0 < r.arrival:
+                pass
+            gd = singles[r.instance] if r.instance else up_dev[id(r.graph)]
+            f = lbg.bfs if r.kind == serve.KIND_BFS else lbg.sssp
+            f(gd, r.src, workspace=ws1)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0 - r.arrival)
+        wall = time.perf_counter() - t0
+        lat = np.array(lat) * 1e3
+        return {"plain_p50_ms": round(float(np.percentile(lat, 50)), 4),
+                "plain_p99_ms": round(float(np.percentile(lat, 99)), 4),
+                "plain_qps": round(len(reqs) / wall, 2)}
+
     points = []
     for frac in fractions:
         qps = sat * frac
         reqs = serve.poisson_requests(qps, requests_per_point, inst, upload_graphs=uploads,
                                       upload_share=0.25, seed=int(frac * 1000), sources=srcs)
         arena = serve.UploadArena(dg, u.n, u.m, R, NC, MC)
-        rep = serve.Server(eng, inst, upload=arena).run(reqs)
+        rep = serve.Server(eng, inst, upload=arena, plain=lane).run(reqs)
         s = rep.summary()
         s["offered_qps"] = round(qps, 2)
         s["fraction_of_plain_saturation"] = frac
+        s.update(plain_serve(reqs))
         points.append(s)
         log(f"serve {frac:.2f} x saturation: {s}")
     eng.close()
@@ -386,7 +415,10 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
             "workload": f"resident R-MAT scales {list(scales)} (ef 16, symmetrised, weights "
                         f"U[1,255]) + per-request uploaded uniform graphs n in [2^12, 2^16]; "
                         f"Poisson arrivals, 70% BFS / 30% SSSP, 25% uploads; "
-                        f"{requests_per_point} requests per point; gteps counts instance arcs"}
+                        f"{requests_per_point} requests per point; gteps counts instance arcs; "
+                        f"instances of >= {big_arcs} arcs are served by plain solves on a second "
+                        f"stream, the rest are batched; plain_* = the same arrivals served FCFS "
+                        f"by one plain call each"}
 
 
 def main():

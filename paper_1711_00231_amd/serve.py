@@ -10,12 +10,21 @@ resources return to the pools, and latency = completion - arrival is
 recorded.  Admission is first-come first-served: a request that does not fit
 blocks the ones behind it, so no request starves.
 
-The engine is injected: anything with submit/step/release/rows works, which
-is how the scheduling logic is tested without a GPU.
+Admission is size-aware when a PlainLane is given: a query on a large
+resident instance already fills the GPU by itself, so batching it would only
+add per-level synchronisation; such queries are served first-come
+first-served by one plain solve each, on a stream and host thread of their
+own, while the engine keeps batching the small ones on the same GPU.
+
+The engine and the plain solver are injected: anything with
+submit/step/release/rows works, which is how the scheduling logic is tested
+without a GPU.
 """
 from __future__ import annotations
 
 import bisect
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -107,20 +116,88 @@ class ServeReport:
         return out
 
 
+class PlainLane:
+    """Queries on large instances, served first-come first-served by one
+    plain solve each from a worker thread.  solve(request, keep) runs the
+    query to completion (the GPU binding releases the interpreter lock
+    meanwhile) and returns its result row when keep is true; `big_arcs` is
+    the size from which an instance goes here."""
+
+    def __init__(self, solve, big_arcs: int):
+        self.solve = solve
+        self.big_arcs = int(big_arcs)
+        self._q: queue.Queue = queue.Queue()
+        self._lock = threading.Lock()
+        self._done: list = []
+        self._pending = 0
+        self._thread = None
+        self._error = None
+
+    def wants(self, arcs: int) -> bool:
+        return arcs >= self.big_arcs
+
+    def start(self, clock, t0: float, keep_results: bool) -> None:
+        def work():
+            while True:
+                r = self._q.get()
+                if r is None:
+                    return
+                try:
+                    res = self.solve(r, keep_results)
+                except Exception as exc:  # surfaced by the serving loop
+                    with self._lock:
+                        self._error = exc
+                        self._pending -= 1
+                    continue
+                r.done = clock() - t0
+                if keep_results:
+                    r.result = res
+                with self._lock:
+                    self._done.append(r)
+                    self._pending -= 1
+
+        self._thread = threading.Thread(target=work, daemon=True)
+        self._thread.start()
+
+    def submit(self, r: Request) -> None:
+        with self._lock:
+            self._pending += 1
+        self._q.put(r)
+
+    def busy(self) -> bool:
+        with self._lock:
+            return self._pending > 0
+
+    def drain(self) -> list:
+        with self._lock:
+            if self._error is not None:
+                raise self._error
+            out, self._done = self._done, []
+        return out
+
+    def stop(self) -> None:
+        if self._thread is not None:
+            self._q.put(None)
+            self._thread.join()
+            self._thread = None
+
+
 class Server:
     """FCFS admission + continuous batching over an engine.
 
     instances: name -> Instance (node range of a resident graph in the packed
-    CSR).  upload: optional UploadArena for per-request graphs.
+    CSR).  upload: optional UploadArena for per-request graphs.  plain:
+    optional PlainLane for queries on large resident instances.
     """
 
     def __init__(self, engine, instances: dict, upload=None, levels_per_step: int = 1,
-                 keep_results: bool = False):
+                 keep_results: bool = False, plain: PlainLane | None = None):
         self.engine = engine
         self.instances = instances
         self.upload = upload
         self.levels_per_step = int(levels_per_step)
         self.keep_results = keep_results
+        self.plain = plain
         self.rows = RowAllocator(engine.max_rows)
         self.inflight: dict[int, Request] = {}
 
@@ -129,6 +206,10 @@ class Server:
         if r.instance is not None:
             inst = self.instances[r.instance]
             lo, hi, arcs = inst.lo, inst.hi, inst.arcs
+            if self.plain is not None and self.plain.wants(arcs):
+                r.admitted, r.arcs, r.length = now, arcs, hi - lo
+                self.plain.submit(r)
+                return True
         else:
             if self.upload is None:
                 raise ValueError("request carries a graph but the server has no upload arena")
@@ -173,29 +254,43 @@ class Server:
         pending = list(requests)
         report = ServeReport()
         t0 = clock()
+        lane = self.plain
+        if lane is not None:
+            lane.start(clock, t0, self.keep_results)
         i = 0
-        while i < len(pending) or self.inflight:
-            now = clock() - t0
-            while i < len(pending) and (replay or pending[i].arrival <= now):
-                if not self._try_admit(pending[i], now):
-                    break
-                i += 1
-            if not self.inflight:
-                if i >= len(pending):
-                    break
-                if replay or pending[i].arrival <= clock() - t0:
-                    # it arrived, nothing runs, and it still does not fit
-                    raise RuntimeError(f"request {pending[i].rid} can never be admitted "
-                                       "(larger than the server's capacity)")
-                wait = pending[i].arrival - (clock() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.001))
-                continue
-            done = self.engine.step(self.levels_per_step)
-            report.steps += 1
-            now = clock() - t0
-            for slot in done:
-                report.completed.append(self._complete(slot, now))
+        try:
+            while i < len(pending) or self.inflight or (lane is not None and lane.busy()):
+                now = clock() - t0
+                blocked = False  # an arrived request did not fit
+                while i < len(pending) and (replay or pending[i].arrival <= now):
+                    if not self._try_admit(pending[i], now):
+                        blocked = True
+                        break
+                    i += 1
+                if lane is not None:
+                    report.completed.extend(lane.drain())
+                if not self.inflight:
+                    if i >= len(pending):
+                        if lane is not None and lane.busy():
+                            time.sleep(0.0001)
+                        continue
+                    if blocked and not (lane is not None and lane.busy()):
+                        # it arrived, nothing runs, and it still does not fit
+                        raise RuntimeError(f"request {pending[i].rid} can never be admitted "
+                                           "(larger than the server's capacity)")
+                    wait = pending[i].arrival - (clock() - t0)
+                    time.sleep(min(max(wait, 0.0), 0.001) if wait > 0 else 0.0001)
+                    continue
+                done = self.engine.step(self.levels_per_step)
+                report.steps += 1
+                now = clock() - t0
+                for slot in done:
+                    report.completed.append(self._complete(slot, now))
+        finally:
+            if lane is not None:
+                lane.stop()
+        if lane is not None:
+            report.completed.extend(lane.drain())
         report.wall = clock() - t0
         return report
 
@@ -281,3 +376,31 @@ class UploadArena:
                 torch.from_numpy((g.cols.astype(np.int64) + lo).astype(np.int32)).to(dev))
             self.dg.weights[a0: a0 + g.m].copy_(torch.from_numpy(g.weights.view(np.int32)).to(dev))
         return lo, lo + g.n, g.m
+
+
+def gpu_plain_lane(graphs: dict, big_arcs: int) -> PlainLane:
+    """A PlainLane over resident device graphs (instance name -> DeviceGraph
+    with local node ids): each query runs as one balanced BFS/SSSP solve on
+    a stream of its own."""
+    import torch
+
+    from . import lbg
+
+    gs = list(graphs.values())
+    dev = gs[0].offsets.device
+    stream = torch.cuda.Stream(device=dev)
+    ws = lbg.Workspace(dev)
+    ws.get(max(max(lbg.workspace_bytes(g.n, g.m, "balanced", False),
+                   lbg.workspace_bytes(g.n, g.m, "balanced", True)) for g in gs))
+    out = torch.empty(max(g.n for g in gs), dtype=torch.int32, device=dev)
+
+    def solve(r, keep):
+        g = graphs[r.instance]
+        f = lbg.bfs if r.kind == KIND_BFS else lbg.sssp
+        f(g, r.src, out=out[: g.n], workspace=ws, stream=stream)
+        if not keep:
+            return None
+        with torch.cuda.stream(stream):
+            return out[: g.n].cpu().numpy()
+
+    return PlainLane(solve, big_arcs)

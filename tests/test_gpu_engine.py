@@ -91,4 +91,18 @@ def test_server_loop_on_gpu_with_uploads():
     for r in rep.completed:
         g = gs[int(r.instance[1:])] if r.instance is not None else r.graph
         assert np.array_equal(r.result, _expected(g, r.src, r.kind)), r.rid
+    # size-aware admission: the largest instance is served by plain solves on
+    # a second stream while the engine batches the rest, concurrently
+    big = max(inst, key=lambda k: inst[k].arcs)
+    lane = serve.gpu_plain_lane({big: lbg.DeviceGraph.from_numpy(gs[int(big[1:])].offsets,
+                                                                 gs[int(big[1:])].cols,
+                                                                 gs[int(big[1:])].weights)},
+                                big_arcs=inst[big].arcs)
+    reqs = serve.poisson_requests(5e3, 40, inst, upload_graphs=uploads, upload_share=0.3, seed=8)
+    rep = serve.Server(eng, inst, upload=arena, keep_results=True, plain=lane).run(reqs, replay=True)
+    assert len(rep.completed) == 40
+    assert any(r.slot < 0 for r in rep.completed)
+    for r in rep.completed:
+        g = gs[int(r.instance[1:])] if r.instance is not None else r.graph
+        assert np.array_equal(r.result, _expected(g, r.src, r.kind)), r.rid
     eng.close()

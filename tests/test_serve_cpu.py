@@ -169,3 +169,41 @@ def test_upload_region_layout_matches_graph():
             assert np.array_equal(O.dijkstra(sub, sc, sw, s), O.dijkstra(g.offsets, g.cols, g.weights, s))
         # the whole packed graph stays valid (oracle rejects bad CSR)
         O.bfs(po, DG.cols.numpy(), 0)
+
+
+def test_plain_lane_takes_large_instances():
+    """Queries on instances at or above big_arcs go to the plain lane (a
+    worker thread), the rest to the batched engine; all complete with the
+    oracle's answers, whichever path served them."""
+    gs, u, inst = _setup()
+    big = max(inst, key=lambda k: inst[k].arcs)
+
+    def solve(r, keep):
+        g = gs[int(r.instance[1:])]
+        if r.kind == serve.KIND_BFS:
+            return O.bfs(g.offsets, g.cols, r.src)
+        return O.dijkstra(g.offsets, g.cols, g.weights, r.src).view(np.int32)
+
+    lane = serve.PlainLane(solve, big_arcs=inst[big].arcs)
+    eng = FakeEngine(u, max_queries=3, max_rows=6000)
+    reqs = serve.poisson_requests(1e4, 50, inst, seed=13)
+    rep = serve.Server(eng, inst, keep_results=True, plain=lane).run(reqs, replay=True)
+    assert len(rep.completed) == 50 and not eng.slots
+    _check_results(rep, gs)
+    via_lane = [r for r in rep.completed if r.slot < 0]
+    assert via_lane and all(r.instance == big for r in via_lane)
+    assert all(r.instance != big for r in rep.completed if r.slot >= 0)
+    assert all(r.done >= r.admitted for r in rep.completed)  # replay admits ahead of arrival
+
+
+def test_plain_lane_error_surfaces():
+    gs, u, inst = _setup()
+
+    def solve(r, keep):
+        raise ValueError("solver failed")
+
+    lane = serve.PlainLane(solve, big_arcs=0)  # everything resident goes to the lane
+    eng = FakeEngine(u, max_queries=2, max_rows=6000)
+    reqs = serve.poisson_requests(1e4, 5, inst, seed=3)
+    with pytest.raises(ValueError, match="solver failed"):
+        serve.Server(eng, inst, plain=lane).run(reqs, replay=True)
