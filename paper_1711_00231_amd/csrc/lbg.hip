@@ -43,7 +43,7 @@ int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
 // Workspace layout.  All offsets 256-byte aligned.
 struct Layout {
-  size_t ctl, visited, seen[2], xfilter, dstate, node[2], eprefix[2], estart[2], tile[2], total;
+  size_t ctl, visited, seen[2], xfilter, dstate, d16, node[2], eprefix[2], estart[2], tile[2], total;
   uint32_t node_cap, tile_cap, edge_cap;
 };
 
@@ -60,6 +60,7 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
   const size_t words = (static_cast<size_t>(n) + 31) / 32;
   if (is_sssp) {
     L.dstate = take(sizeof(unsigned long long) * static_cast<size_t>(n));
+    L.d16 = take(sizeof(uint16_t) * static_cast<size_t>(n));
   } else {
     L.visited = take(sizeof(uint32_t) * words);
     L.seen[0] = take(sizeof(uint32_t) * words);
@@ -253,6 +254,7 @@ int solve(const Problem& P) {
   if (P.is_sssp) {
     a.dist = static_cast<uint32_t*>(P.out);
     a.dstate = reinterpret_cast<unsigned long long*>(ws + Lay.dstate);
+    a.d16 = reinterpret_cast<uint16_t*>(ws + Lay.d16);
   } else {
     a.levels = static_cast<int32_t*>(P.out);
     a.visited = reinterpret_cast<uint32_t*>(ws + Lay.visited);

@@ -90,6 +90,7 @@ struct KArgs {
   uint32_t* seen[2];     // BFS: read-only-per-level snapshots of `visited` (double-buffered)
   uint32_t* xfilter;     // BFS: per-XCD advisory copy of `visited`, kXcds x words
   unsigned long long* dstate;  // SSSP: (distance << 32) | iteration of last improvement
+  uint16_t* d16;         // SSSP single solves: filter, min(an upper bound of the distance, 0xffff)
   Frontier fr[2];
   Ctl* ctl;
   uint32_t n;
@@ -116,6 +117,12 @@ constexpr unsigned kErrNodeCap = 1u, kErrTileCap = 2u, kErrEdgeCap = 4u, kErrBad
 // arithmetic, which matters with 16 loads in flight per lane.  Valid when
 // every array the kernel touches is below 4 GiB (n < 2^29, m < 2^30); the
 // host picks the wide form otherwise.
+// 16-bit distance filter: any value stored is at least the node's current
+// distance (values only decrease); 0xffff carries no information.
+constexpr uint32_t kF16None = 0xffffu;
+__device__ __forceinline__ uint32_t f16_bound(uint16_t f) { return f < kF16None ? f : 0xffffffffu; }
+__device__ __forceinline__ uint16_t f16_of(uint32_t d) { return static_cast<uint16_t>(d < kF16None ? d : kF16None); }
+
 template <bool kNarrow, typename T>
 __device__ __forceinline__ T* at(T* base, uint32_t idx) {
   if constexpr (kNarrow)

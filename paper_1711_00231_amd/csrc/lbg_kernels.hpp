@@ -24,10 +24,13 @@
 //    whether the arc improved the node and whether the node is already queued
 //    for this iteration (the worklist condensing concern of Section II-B is
 //    handled at push time, with no second atomic).  The per-arc filter reads
-//    the caller's 4-byte output array instead of the 8-byte state (half the
-//    random-read footprint); winners refresh it with plain stores, so it may
-//    lag the state but never undercuts it, and the epilogue rewrites it from
-//    the state.  A frontier node's own distance is always read from the state.
+//    a 2-byte copy, min(distance, 0xffff), instead of the 8-byte state (a
+//    quarter of the random-read footprint: 8 MiB at scale 22, half of what an
+//    XCD's L2 holds); winners refresh it with plain stores, so it may lag the
+//    state but never undercuts it, and 0xffff (too large, or unknown) never
+//    filters.  Batched rows filter on their 4-byte output row instead.  A
+//    frontier node's own distance is always read from the state, and the
+//    epilogue writes the output from the state.
 // Plain reads may be stale inside a launch; values only move one way (bits
 // set, distances decrease), so a stale read can only cost an extra atomic,
 // never a missed update.
@@ -127,12 +130,12 @@ __device__ __forceinline__ bool relax(const KArgs& a, uint32_t L, int32_t v, uin
     ++*upd;
   } else {
     const uint32_t alt = du + w;
-    if (alt >= a.dist[v]) return false;
+    if (alt >= f16_bound(a.d16[v])) return false;
     const unsigned long long mine = (static_cast<unsigned long long>(alt) << 32) | (L + 1);
     ++*atom;
     const unsigned long long old = atomicMin(&a.dstate[v], mine);
     if (alt >= static_cast<uint32_t>(old >> 32)) return false;
-    a.dist[v] = alt;  // filter copy; may lag the state, never undercuts it
+    a.d16[v] = f16_of(alt);  // filter; may lag the state, never undercuts it
     ++*upd;
     if (static_cast<uint32_t>(old) == L + 1) return false;  // already queued this iteration
   }
@@ -154,6 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
       a.dstate[v] = (v == static_cast<uint32_t>(src)) ? 0ull
                                                       : (static_cast<unsigned long long>(kSsspInf) << 32);
       a.dist[v] = (v == static_cast<uint32_t>(src)) ? 0u : kSsspInf;
+      a.d16[v] = (v == static_cast<uint32_t>(src)) ? 0 : static_cast<uint16_t>(kF16None);
     } else {
       a.levels[v] = (v == static_cast<uint32_t>(src)) ? 0 : static_cast<int32_t>(kBfsInf);
     }
@@ -474,9 +478,11 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         cd[r] = 0u;
-        if (vv[r] >= 0)
-          cd[r] = (kMulti && bfsq[kMulti ? r : 0]) ? *at<kNarrow>(static_cast<const uint32_t*>(a.visited), row[r] >> 5)
-                                                   : *at<kNarrow>(static_cast<const uint32_t*>(a.dist), row[r]);
+        if (vv[r] >= 0) {
+          if (!kMulti) cd[r] = f16_bound(*at<kNarrow>(static_cast<const uint16_t*>(a.d16), row[r]));
+          else if (bfsq[kMulti ? r : 0]) cd[r] = *at<kNarrow>(static_cast<const uint32_t*>(a.visited), row[r] >> 5);
+          else cd[r] = *at<kNarrow>(static_cast<const uint32_t*>(a.dist), row[r]);
+        }
       }
       unsigned long long old[kItems];
 #pragma unroll
@@ -507,7 +513,10 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
           push[r] = won;
         } else {
           const bool better = vv[r] >= 0 && alt < static_cast<uint32_t>(old[r] >> 32);
-          if (better) *at<kNarrow>(a.dist, row[r]) = alt;  // filter copy (see top of file)
+          if (better) {  // filter (see top of file)
+            if (kMulti) *at<kNarrow>(a.dist, row[r]) = alt;
+            else *at<kNarrow>(a.d16, row[r]) = f16_of(alt);
+          }
           upd += better ? 1u : 0u;
           push[r] = better && static_cast<uint32_t>(old[r]) != L + 1;
         }
@@ -793,7 +802,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t 
               atomicMin(at<kNarrow>(a.dstate, static_cast<uint32_t>(vv[r])),
                         (static_cast<unsigned long long>(alt) << 32) | (L + 1));
           if (alt < static_cast<uint32_t>(old >> 32)) {
-            *at<kNarrow>(a.dist, vv[r]) = alt;  // filter copy for one-level launches
+            *at<kNarrow>(a.d16, vv[r]) = f16_of(alt);  // filter of the one-level launches
             ++upd;
             win[r] = static_cast<uint32_t>(old) != L + 1;  // not yet queued this level
           }

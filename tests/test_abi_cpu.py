@@ -37,7 +37,7 @@ def test_workspace_formulas():
     ctl = al(128 + 8 * 128)
     words = (n + 31) // 32
     bfs_state = 3 * al(4 * words) + al(4 * words * 8)   # visited + 2 snapshots + per-XCD filters
-    sssp_state = al(8 * n)                          # packed (distance, iteration)
+    sssp_state = al(8 * n) + al(2 * n)              # packed (distance, iteration) + 16-bit filter
     # BFS, node-based / balanced: node state + 2 x (3 node arrays + tile marks)
     tiles = (m + T - 1) // T + 2
     exp_bfs = ctl + bfs_state + 2 * (3 * al(4 * n) + al(4 * tiles))
