@@ -20,6 +20,11 @@
  *   LBG_BALANCED  workload decomposition: the frontier's edges are cut into
  *                 equal contiguous tiles that ignore node boundaries, so hubs
  *                 are shared by many workgroups (WD)
+ *   LBG_BINNED    degree bins: a node with more than `mdt` out-arcs enters
+ *                 the worklist as pieces of at most mdt arcs (the node
+ *                 splitting of Section III-B, applied to worklist entries),
+ *                 and each entry is expanded by one lane, one wavefront or one
+ *                 workgroup according to its length (lbg_set_bins)
  *   LBG_AUTO      currently LBG_BALANCED
  *
  * Conventions for every entry point
@@ -66,7 +71,8 @@ typedef enum {
   LBG_AUTO = 0,
   LBG_NODE = 1,
   LBG_EDGE = 2,
-  LBG_BALANCED = 3
+  LBG_BALANCED = 3,
+  LBG_BINNED = 4
 } lbg_strategy;
 
 /* Counters of one solve (host struct, filled when `stats` is not NULL).
@@ -118,6 +124,44 @@ int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weight
  * or LBG_EINVAL (with a message naming the first kind of defect found). */
 int lbg_validate_csr(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m,
                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Degree-bin parameters of LBG_BINNED solves (process-wide).
+ *   mdt      split size: a node with more out-arcs is queued as ceil(deg/mdt)
+ *            pieces, the first deg % pieces of them one arc longer (0 = no
+ *            splitting; otherwise at least 64)
+ *   t_wave   pieces longer than this are expanded by one wavefront
+ *   t_block  pieces longer than this are expanded by one workgroup
+ * lbg_set_bins returns LBG_EINVAL (and changes nothing) for mdt in [1, 63]
+ * or t_wave > t_block; it applies to solves that start afterwards.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t mdt, t_wave, t_block;
+} lbg_bins;
+
+int lbg_set_bins(const lbg_bins* bins);
+void lbg_get_bins(lbg_bins* bins);
+
+/* The MDT of Section III-B computed on the device from the CSR offsets: the
+ * out-degrees are histogrammed into 10 bins of width maxDegree/10 numbered
+ * from 1 (bin of degree d: max(1, ceil(10 d / maxDegree))), k = the fullest
+ * bin (ties to the smaller), MDT = max(1, floor(k * maxDegree / 10)).
+ * workspace: lbg_workspace_bytes(n, m, LBG_NODE, 0) bytes.  *mdt_out is a
+ * host int32; *max_degree_out (nullable) receives maxDegree. */
+int lbg_degree_mdt(const int32_t* offsets, int32_t n, int64_t m, void* workspace,
+                   size_t workspace_bytes, int32_t* mdt_out, int32_t* max_degree_out, void* stream);
+
+/* Autotuner of the degree bins on the caller's graph: times LBG_BINNED BFS
+ * (and SSSP when weights is not NULL) from the given host array of sources
+ * for split sizes seeded by lbg_degree_mdt and a small grid of t_wave /
+ * t_block values, keeps the fastest set (lbg_set_bins) and returns it in
+ * *best.  out: device int32[n] scratch; workspace: at least
+ * lbg_workspace_bytes(n, m, LBG_BINNED, 1) bytes.  Results of the timed
+ * solves are discarded; the call synchronises `stream`. */
+int lbg_autotune_bins(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
+                      int32_t n, int64_t m, const int32_t* sources, int32_t num_sources,
+                      int32_t* out, void* workspace, size_t workspace_bytes, lbg_bins* best,
+                      void* stream);
 
 /* Human-readable message for the last non-OK return on the calling thread. */
 const char* lbg_last_error(void);

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -38,7 +39,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_BALANCED; }
+bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_BINNED; }
 int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
 // Workspace layout.  All offsets 256-byte aligned.
@@ -71,12 +72,13 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
     L.edge_cap = static_cast<uint32_t>(m);
     for (int b = 0; b < 2; ++b) L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(m > 0 ? m : 1));
   } else {
-    L.node_cap = static_cast<uint32_t>(n);
+    // split hubs add at most m / kMinMdt entries per level
+    L.node_cap = static_cast<uint32_t>(n + (s == LBG_BINNED ? m / lbg::kMinMdt + 1 : 0));
     L.tile_cap = static_cast<uint32_t>((m + lbg::kMinTile - 1) / lbg::kMinTile + 2);
     for (int b = 0; b < 2; ++b) {
-      L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(n));
-      L.eprefix[b] = take(sizeof(uint32_t) * static_cast<size_t>(n));
-      L.estart[b] = take(sizeof(int32_t) * static_cast<size_t>(n));
+      L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(L.node_cap));
+      L.eprefix[b] = take(sizeof(uint32_t) * static_cast<size_t>(L.node_cap));
+      L.estart[b] = take(sizeof(int32_t) * static_cast<size_t>(L.node_cap));
       L.tile[b] = take(sizeof(int32_t) * static_cast<size_t>(L.tile_cap));
     }
   }
@@ -115,8 +117,8 @@ int resident_grid(K kernel) {
 }
 
 struct Grids {
-  int bal[2][2], node[2], edge[2], multi[2];  // bal[is_sssp][narrow], multi[narrow]
-  bool small[2][2];                           // small-frontier kernel fits the device
+  int bal[2][2], node[2], edge[2], multi[2], binned[2];  // bal[is_sssp][narrow], multi[narrow]
+  bool small[2][2];                                      // small-frontier kernel fits the device
 };
 
 // The small-frontier kernel holds its frontier in LDS (about 100 KiB for
@@ -148,6 +150,8 @@ const Grids& grids() {
     g[dev].node[1] = resident_grid(lbg::k_expand_node<true>);
     g[dev].edge[0] = resident_grid(lbg::k_expand_edge<false>);
     g[dev].edge[1] = resident_grid(lbg::k_expand_edge<true>);
+    g[dev].binned[0] = resident_grid(lbg::k_expand_binned<false>);
+    g[dev].binned[1] = resident_grid(lbg::k_expand_binned<true>);
     g[dev].multi[0] = resident_grid(lbg::k_expand_balanced<true, false, true>);
     g[dev].multi[1] = resident_grid(lbg::k_expand_balanced<true, true, true>);
     g[dev].small[0][0] = fits_lds(lbg::k_expand_small<false, false>);
@@ -160,6 +164,10 @@ const Grids& grids() {
 }
 
 int grid_blocks() { return grids().bal[0][1]; }
+
+// Degree-bin parameters of LBG_BINNED solves (process-wide; lbg_set_bins).
+std::mutex g_bins_mu;
+lbg_bins g_bins{4096, 32, 1024};
 
 // Host side of the profiling counters (see lbg_profile_enable).
 std::mutex g_prof_mu;
@@ -277,6 +285,12 @@ int solve(const Problem& P) {
   a.node_cap = Lay.node_cap;
   a.tile_cap = Lay.tile_cap;
   a.edge_cap = Lay.edge_cap;
+  if (strat == LBG_BINNED) {
+    std::lock_guard<std::mutex> lk(g_bins_mu);
+    a.mdt = static_cast<uint32_t>(g_bins.mdt);
+    a.t_wave = static_cast<uint32_t>(g_bins.t_wave);
+    a.t_block = static_cast<uint32_t>(g_bins.t_block);
+  }
   bool profiling;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -310,6 +324,7 @@ int solve(const Problem& P) {
       switch (strat) {
         case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<true>), dim3(GR.node[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<true>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         default:
           if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
           else hipLaunchKernelGGL((lbg::k_expand_balanced<true, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
@@ -319,6 +334,7 @@ int solve(const Problem& P) {
       switch (strat) {
         case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<false>), dim3(GR.node[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<false>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<false>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         default:
           if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<false, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
           else hipLaunchKernelGGL((lbg::k_expand_balanced<false, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
@@ -961,6 +977,111 @@ int lbg_validate_csr(const int32_t* offsets, const int32_t* cols, int32_t n, int
 }
 
 const char* lbg_last_error(void) { return g_err; }
+
+int lbg_set_bins(const lbg_bins* bins) {
+  if (!bins) return fail(LBG_EINVAL, "null bins");
+  if (bins->mdt < 0 || (bins->mdt > 0 && bins->mdt < static_cast<int32_t>(lbg::kMinMdt)) ||
+      bins->t_wave < 0 || bins->t_block < 0 || bins->t_wave > bins->t_block)
+    return fail(LBG_EINVAL, "need mdt = 0 or mdt >= %u, and 0 <= t_wave <= t_block", lbg::kMinMdt);
+  std::lock_guard<std::mutex> lk(g_bins_mu);
+  g_bins = *bins;
+  return LBG_OK;
+}
+
+void lbg_get_bins(lbg_bins* bins) {
+  if (!bins) return;
+  std::lock_guard<std::mutex> lk(g_bins_mu);
+  *bins = g_bins;
+}
+
+int lbg_degree_mdt(const int32_t* offsets, int32_t n, int64_t m, void* workspace,
+                   size_t workspace_bytes, int32_t* mdt_out, int32_t* max_degree_out, void* stream) {
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX)
+    return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
+  if (!offsets || !workspace || !mdt_out) return fail(LBG_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  if (workspace_bytes < layout(n, m, LBG_NODE, 0).total) return fail(LBG_ENOMEM, "workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ctl* ctl = static_cast<Ctl*>(workspace);
+  Ctl* host = pinned_ctl();
+  if (!host) return fail(LBG_EHIP, "hipHostMalloc of the readback word failed");
+  const int blocks = static_cast<int>(
+      std::min<int64_t>(std::max<int64_t>((static_cast<int64_t>(n) + lbg::kBlock - 1) / lbg::kBlock, 1), 4096));
+  hipLaunchKernelGGL(lbg::k_deg_clear, dim3(1), dim3(lbg::kBlock), 0, st, ctl);
+  hipLaunchKernelGGL(lbg::k_deg_max, dim3(blocks), dim3(lbg::kBlock), 0, st, offsets, static_cast<uint32_t>(n), ctl);
+  hipLaunchKernelGGL(lbg::k_deg_hist, dim3(blocks), dim3(lbg::kBlock), 0, st, offsets, static_cast<uint32_t>(n), ctl);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int64_t mx = host->deg_max;
+  int best = 1;
+  int64_t best_count = -1;
+  for (int b = 1; b <= lbg::kMdtBins; ++b) {
+    const int64_t cnt = xsum(host, b - 1);
+    if (cnt > best_count) {  // strictly greater: ties go to the smaller bin
+      best_count = cnt;
+      best = b;
+    }
+  }
+  *mdt_out = static_cast<int32_t>(std::max<int64_t>(1, best * mx / lbg::kMdtBins));
+  if (max_degree_out) *max_degree_out = static_cast<int32_t>(mx);
+  return LBG_OK;
+}
+
+int lbg_autotune_bins(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
+                      int32_t n, int64_t m, const int32_t* sources, int32_t num_sources,
+                      int32_t* out, void* workspace, size_t workspace_bytes, lbg_bins* best,
+                      void* stream) {
+  if (!sources || num_sources <= 0 || !out || !best) return fail(LBG_EINVAL, "null or empty argument");
+  if (n <= 0 || m < 0 || m > INT32_MAX) return fail(LBG_EINVAL, "bad graph size");
+  if (workspace_bytes < layout(n, m, LBG_BINNED, 1).total || workspace_bytes < layout(n, m, LBG_BINNED, 0).total)
+    return fail(LBG_ENOMEM, "workspace too small");
+  int32_t seed = 0;
+  int rc = lbg_degree_mdt(offsets, n, m, workspace, workspace_bytes, &seed, nullptr, stream);
+  if (rc) return rc;
+  std::vector<int32_t> mdts = {std::max<int32_t>(seed, static_cast<int32_t>(lbg::kMinMdt)), 256, 1024, 4096, 16384};
+  std::sort(mdts.begin(), mdts.end());
+  mdts.erase(std::unique(mdts.begin(), mdts.end()), mdts.end());
+  lbg_bins saved;
+  lbg_get_bins(&saved);
+  auto run_all = [&]() -> int {
+    for (int32_t k = 0; k < num_sources; ++k) {
+      int r = lbg_bfs(offsets, cols, n, m, sources[k], out, workspace, workspace_bytes, LBG_BINNED,
+                      nullptr, nullptr, stream);
+      if (r) return r;
+      if (weights) {
+        r = lbg_sssp(offsets, cols, weights, n, m, sources[k], reinterpret_cast<uint32_t*>(out), workspace,
+                     workspace_bytes, LBG_BINNED, nullptr, nullptr, stream);
+        if (r) return r;
+      }
+    }
+    return LBG_OK;
+  };
+  if ((rc = run_all()) != LBG_OK) return rc;  // warm-up
+  double best_s = -1.0;
+  lbg_bins pick = saved;
+  for (int32_t mdt : mdts)
+    for (int32_t tw : {16, 32, 64})
+      for (int32_t tb : {256, 1024}) {
+        const lbg_bins b{mdt, tw, tb};
+        if ((rc = lbg_set_bins(&b)) != LBG_OK) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        if ((rc = run_all()) != LBG_OK) {
+          (void)lbg_set_bins(&saved);
+          return rc;
+        }
+        const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (best_s < 0 || t < best_s) {
+          best_s = t;
+          pick = b;
+        }
+      }
+  (void)lbg_set_bins(&pick);
+  *best = pick;
+  return LBG_OK;
+}
 
 void lbg_profile_enable(int32_t enable, int32_t reset) {
   std::lock_guard<std::mutex> lk(g_prof_mu);

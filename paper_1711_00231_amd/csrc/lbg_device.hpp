@@ -56,7 +56,9 @@ struct Ctl {
   unsigned int pad0;
   unsigned long long p_frontier_entries;  // the part of the two totals above
   unsigned long long p_edges_scanned;     // done by the small-frontier kernel
-  unsigned long long pad1[7];
+  unsigned int deg_max;       // lbg_degree_mdt
+  unsigned int pad2;
+  unsigned long long pad1[6];
   // [x][0] updates, [x][1] global atomics issued; [x][2], [x][3] the same for
   // levels run by the small-frontier kernel
   unsigned long long xstat[kXcds][16];
@@ -104,7 +106,25 @@ struct KArgs {
   uint32_t num_queries;
   uint32_t rows;         // batched solves: total elements of node state
   uint32_t* qlast;       // engine: per query, the last level that holds one of its entries
+  // Degree-binned strategy: a node with more than `mdt` out-arcs is queued as
+  // ceil(deg / mdt) pieces (0 = no splitting); a piece longer than t_block
+  // is expanded by a workgroup, longer than t_wave by a wavefront, else by
+  // one lane.
+  uint32_t mdt, t_wave, t_block;
 };
+
+// Pieces of a node with d out-arcs under split size mdt, and piece k's
+// offset within the node's arcs and length: the first d % p pieces carry one
+// arc more (node splitting, Section III-B).
+__device__ __forceinline__ uint32_t split_count(uint32_t d, uint32_t mdt) {
+  return (mdt != 0u && d > mdt) ? (d + mdt - 1u) / mdt : 1u;
+}
+__device__ __forceinline__ void split_piece(uint32_t d, uint32_t p, uint32_t k, uint32_t* off,
+                                            uint32_t* len) {
+  const uint32_t q = d / p, r = d % p;
+  *off = k * q + (k < r ? k : r);
+  *len = q + (k < r ? 1u : 0u);
+}
 
 // Ctl::error bits.  None can trip for a well-formed CSR; they turn what
 // would otherwise be an out-of-bounds access into an LBG_EOVERFLOW return.
@@ -235,6 +255,54 @@ struct WaveQueue {
           }
         } else {
           atomicOr(&a.ctl->error, kErrNodeCap);
+        }
+      }
+    }
+    count = 0;
+  }
+
+  // Node worklist flush with node splitting: a queued node of degree d is
+  // written as split_count(d, a.mdt) entries (node, first arc of the piece,
+  // edge prefix), reserved with the same single packed atomic.
+  __device__ __forceinline__ void flush_split(const KArgs& a, Frontier out, int ctr_idx) {
+    if (count == 0) return;
+    const uint32_t lane = lane_id();
+    uint32_t pre_n[kQueue / 64], pre_e[kQueue / 64];
+    uint32_t cn = 0, ce = 0;
+#pragma unroll
+    for (int r = 0; r < kQueue / 64; ++r) {
+      const uint32_t k = r * 64 + lane;
+      const uint32_t d = k < count ? static_cast<uint32_t>(qd[k]) : 0u;
+      const uint32_t pc = k < count ? split_count(d, a.mdt) : 0u;
+      const uint32_t in = wave_incl_scan(pc), ie = wave_incl_scan(d);
+      pre_n[r] = cn + in - pc;
+      pre_e[r] = ce + ie - d;
+      cn += __shfl(in, 63, 64);
+      ce += __shfl(ie, 63, 64);
+    }
+    unsigned long long base = 0;
+    if (lane == 0)
+      base = atomicAdd(&a.ctl->ctr[ctr_idx], (static_cast<unsigned long long>(cn) << 32) | ce);
+    base = bcast64(base, 0);
+    const uint32_t nb = static_cast<uint32_t>(base >> 32);
+    const uint32_t eb = static_cast<uint32_t>(base);
+#pragma unroll
+    for (int r = 0; r < kQueue / 64; ++r) {
+      const uint32_t k = r * 64 + lane;
+      if (k < count) {
+        const uint32_t d = static_cast<uint32_t>(qd[k]);
+        const uint32_t pc = split_count(d, a.mdt);
+        for (uint32_t j = 0; j < pc; ++j) {
+          const uint32_t i = nb + pre_n[r] + j;
+          uint32_t off, len;
+          split_piece(d, pc, j, &off, &len);
+          if (i < a.node_cap) {
+            if (kWithNode) out.node[i] = qv[k];
+            out.eprefix[i] = eb + pre_e[r] + off;
+            out.estart[i] = qs[k] + static_cast<int32_t>(off);
+          } else {
+            atomicOr(&a.ctl->error, kErrNodeCap);
+          }
         }
       }
     }

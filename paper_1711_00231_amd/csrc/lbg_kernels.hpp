@@ -184,13 +184,17 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
     const uint32_t tiles = (static_cast<uint32_t>(d0) + T - 1) / T;
     for (uint32_t t = gid; t < tiles; t += stride) a.fr[0].tile_node[t] = 0;
   }
+  // the source's entry (pieces of at most a.mdt arcs for the binned strategy)
+  const uint32_t pc = kEdgeWl ? 0u : split_count(static_cast<uint32_t>(d0 > 0 ? d0 : 0), a.mdt);
+  for (uint32_t k = gid; k < pc; k += stride) {
+    uint32_t off, len;
+    split_piece(static_cast<uint32_t>(d0), pc, k, &off, &len);
+    a.fr[0].node[k] = src;
+    a.fr[0].eprefix[k] = off;
+    a.fr[0].estart[k] = s0 + static_cast<int32_t>(off);
+  }
   if (gid == 0) {
-    if (!kEdgeWl) {
-      a.fr[0].node[0] = src;
-      a.fr[0].eprefix[0] = 0u;
-      a.fr[0].estart[0] = s0;
-    }
-    const unsigned long long nodes = kEdgeWl ? 0ull : 1ull;
+    const unsigned long long nodes = kEdgeWl ? 0ull : pc;
     a.ctl->ctr[0] = d0 > 0 ? ((nodes << 32) | static_cast<uint32_t>(d0)) : 0ull;
     a.ctl->ctr[1] = 0ull;
     a.ctl->ctr[2] = 0ull;
@@ -966,6 +970,115 @@ __global__ __launch_bounds__(kBlock) void k_expand_node(KArgs a, uint32_t L) {
   add_stats(a, upd, atom);
 }
 
+// ------------------------------------------------------ degree bins ----
+// Degree-binned expansion: worklist entries are nodes, or pieces of at most
+// a.mdt arcs of a hub (split when pushed; Section III-B's node splitting
+// applied to worklist entries instead of the graph).  Each workgroup takes
+// 256 consecutive entries at a time and bins them by length: pieces longer
+// than t_block are expanded one after another by the whole workgroup,
+// longer than t_wave by one wavefront each, the rest by their own lane
+// (the thread / wavefront / workgroup cooperation of degree-binned
+// load balancing).  Lanes of a cooperating group read consecutive arcs.
+constexpr uint32_t kMinMdt = 64;  // smallest split size (bounds entries per level)
+
+template <bool kSssp>
+__global__ __launch_bounds__(kBlock) void k_expand_binned(KArgs a, uint32_t L) {
+  __shared__ int32_t qS[kWaves][kQueue];
+  __shared__ int32_t qD[kWaves][kQueue];
+  __shared__ int32_t qV[kSssp ? kWaves : 1][kQueue];
+  __shared__ uint32_t bs[2][kBlock], bl[2][kBlock], bdu[2][kSssp ? kBlock : 1];
+  __shared__ uint32_t bcount[2];
+
+  const unsigned long long c = level_begin(a, L);
+  const uint32_t Ef = static_cast<uint32_t>(c);
+  const uint32_t nf = static_cast<uint32_t>(c >> 32);
+  if (Ef == 0) return;
+  if (nf > a.node_cap || Ef > a.m) {
+    if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrNodeCap);
+    return;
+  }
+  if (!kSssp) refresh_seen(a, L);
+  const Frontier cur = a.fr[L & 1];
+  const Frontier nxt = a.fr[(L + 1) & 1];
+  const int nctr = (L + 1) % 3;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  WaveQueue<kSssp> q{qS[wid], qD[wid], qV[kSssp ? wid : 0], 0u};
+  auto flush = [&]() { q.flush_split(a, nxt, nctr); };
+  uint32_t upd = 0, atom = 0;
+
+  // relax the arcs [s + k0, s + len) of one entry, k0 + stride*j per lane
+  auto expand = [&](bool act, uint32_t s, uint32_t len, uint32_t du, uint32_t k0, uint32_t stride,
+                    uint32_t rounds) {
+    for (uint32_t j = 0; j < rounds; ++j) {
+      const uint32_t k = k0 + j * stride;
+      int32_t v = -1, ns = 0, nd = 0;
+      bool want = false;
+      if (act && k < len) {
+        const uint32_t e = s + k;
+        if (e < a.m) {
+          v = a.cols[e];
+          want = relax<kSssp>(a, L, v, du, kSssp ? a.weights[e] : 0u, &upd, &atom, &ns, &nd);
+        } else {
+          atomicOr(&a.ctl->error, kErrBadArc);
+        }
+      }
+      q.push(want, ns, nd, v, flush);
+    }
+  };
+
+  for (uint32_t base = blockIdx.x * kBlock; base < nf; base += gridDim.x * kBlock) {
+    if (tid < 2) bcount[tid] = 0u;
+    __syncthreads();
+    const uint32_t i = base + tid;
+    uint32_t s = 0, len = 0, du = 0;
+    if (i < nf) {
+      const uint32_t p = cur.eprefix[i];
+      const uint32_t pn = (i + 1 < nf) ? cur.eprefix[i + 1] : Ef;
+      s = static_cast<uint32_t>(cur.estart[i]);
+      len = pn - p;
+      if (static_cast<unsigned long long>(s) + len > a.m) {
+        atomicOr(&a.ctl->error, kErrBadArc);
+        len = 0;
+      }
+      if (kSssp) {
+        const unsigned long long sv = a.dstate[cur.node[i]];
+        // already improved this iteration: relaxed with its better distance next time
+        if (static_cast<uint32_t>(sv) == L + 1) len = 0;
+        du = static_cast<uint32_t>(sv >> 32);
+      }
+    }
+    // bins: 0 = workgroup, 1 = wavefront, lane otherwise
+    const int bin = len > a.t_block ? 0 : (len > a.t_wave ? 1 : 2);
+    if (bin < 2) {
+      const uint32_t k = atomicAdd(&bcount[bin], 1u);
+      bs[bin][k] = s;
+      bl[bin][k] = len;
+      if (kSssp) bdu[bin][k] = du;
+    }
+    __syncthreads();
+    const uint32_t nb0 = bcount[0], nb1 = bcount[1];
+    for (uint32_t k = 0; k < nb0; ++k) {  // workgroup bin, one piece at a time
+      const uint32_t l = bl[0][k];
+      expand(true, bs[0][k], l, kSssp ? bdu[0][k] : 0u, tid, kBlock, (l + kBlock - 1) / kBlock);
+    }
+    for (uint32_t k0 = 0; k0 < nb1; k0 += kWaves) {  // wavefront bin
+      const uint32_t k = k0 + wid;
+      const bool act = k < nb1;
+      const uint32_t l = act ? bl[1][k] : 0u;
+      const uint32_t r = static_cast<uint32_t>(wave_max(static_cast<int32_t>((l + 63) / 64)));
+      expand(act, act ? bs[1][k] : 0u, l, (kSssp && act) ? bdu[1][k] : 0u, lane, 64, r);
+    }
+    {  // lane bin
+      const bool act = bin == 2;
+      const uint32_t r = static_cast<uint32_t>(wave_max(static_cast<int32_t>(act ? len : 0u)));
+      expand(act, s, len, du, 0, 1, r);
+    }
+    __syncthreads();
+  }
+  flush();
+  add_stats(a, upd, atom);
+}
+
 // ---------------------------------------------------------- edge (EP) ----
 // Edge-based baseline (Section II-B): the worklist holds arc ids; thread i of
 // the grid-stride loop relaxes arc wl[i] (SSSP reads its source from the COO
@@ -1143,6 +1256,43 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(KArgs a, uint32_t L) {
     for (uint32_t c0 = blockIdx.x * kRowChunk; c0 < static_cast<uint32_t>(qi.row_len); c0 += gridDim.x * kRowChunk)
       finish_chunk(a, qi, c0);
   }
+}
+
+// ------------------------------------------------------ MDT histogram --
+// Out-degree histogram for the MDT rule of Section III-B: maximum degree,
+// then counts of 10 bins of width maxDegree/10 numbered from 1 (bin of
+// degree d: max(1, ceil(10 d / maxDegree))), summed per workgroup in LDS and
+// added to per-XCD lines (xstat[x][bin - 1]).
+constexpr int kMdtBins = 10;
+
+__global__ __launch_bounds__(kBlock) void k_deg_clear(Ctl* ctl) {
+  if (threadIdx.x == 0) ctl->deg_max = 0u;
+  for (int k = threadIdx.x; k < kXcds * 16; k += kBlock) ctl->xstat[k / 16][k % 16] = 0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_deg_max(const int32_t* offsets, uint32_t n, Ctl* ctl) {
+  uint32_t mx = 0;
+  for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock)
+    mx = max(mx, static_cast<uint32_t>(offsets[v + 1] - offsets[v]));
+  mx = static_cast<uint32_t>(wave_max(static_cast<int32_t>(mx)));
+  if (lane_id() == 0 && mx) atomicMax(&ctl->deg_max, mx);
+}
+
+__global__ __launch_bounds__(kBlock) void k_deg_hist(const int32_t* offsets, uint32_t n, Ctl* ctl) {
+  __shared__ uint32_t h[kMdtBins];
+  if (threadIdx.x < kMdtBins) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const unsigned long long mx = ctl->deg_max;
+  for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < n; v += gridDim.x * kBlock) {
+    const unsigned long long d = static_cast<uint32_t>(offsets[v + 1] - offsets[v]);
+    unsigned long long b = mx ? (d * kMdtBins + mx - 1) / mx : 1ull;
+    if (b < 1) b = 1;
+    if (b > kMdtBins) b = kMdtBins;
+    atomicAdd(&h[b - 1], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kMdtBins && h[threadIdx.x])
+    atomicAdd(&ctl->xstat[blockIdx.x % kXcds][threadIdx.x], static_cast<unsigned long long>(h[threadIdx.x]));
 }
 
 // ------------------------------------------------------- CSR validation --

@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbg.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
-AUTO, NODE, EDGE, BALANCED = 0, 1, 2, 3
-STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED}
+AUTO, NODE, EDGE, BALANCED, BINNED = 0, 1, 2, 3, 4
+STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED, "binned": BINNED}
 BFS_INF = 2**31 - 1
 SSSP_INF = 2**32 - 1
 
@@ -43,6 +43,13 @@ KIND_BFS, KIND_SSSP = 0, 1
 class Query(ctypes.Structure):
     _fields_ = [("src", ctypes.c_int32), ("lo", ctypes.c_int32), ("hi", ctypes.c_int32),
                 ("kind", ctypes.c_int32), ("out_off", ctypes.c_int64)]
+
+
+class Bins(ctypes.Structure):
+    _fields_ = [("mdt", ctypes.c_int32), ("t_wave", ctypes.c_int32), ("t_block", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Profile(ctypes.Structure):
@@ -100,6 +107,15 @@ def _load():
                                     ctypes.POINTER(ctypes.c_uint32)]
     lib.lbg_engine_destroy.restype = None
     lib.lbg_engine_destroy.argtypes = [vp]
+    lib.lbg_set_bins.restype = ctypes.c_int
+    lib.lbg_set_bins.argtypes = [ctypes.POINTER(Bins)]
+    lib.lbg_get_bins.restype = None
+    lib.lbg_get_bins.argtypes = [ctypes.POINTER(Bins)]
+    lib.lbg_degree_mdt.restype = ctypes.c_int
+    lib.lbg_degree_mdt.argtypes = [vp, i32, i64, vp, sz, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.lbg_autotune_bins.restype = ctypes.c_int
+    lib.lbg_autotune_bins.argtypes = [vp, vp, vp, i32, i64, ctypes.POINTER(i32), i32, vp, vp, sz,
+                                      ctypes.POINTER(Bins), vp]
     lib.lbg_tile_edges.restype = i32
     lib.lbg_tile_edges.argtypes = []
     lib.lbg_grid_blocks.restype = i32
@@ -373,6 +389,41 @@ def profile_read(which) -> dict:
     p = Profile()
     lib.lbg_profile_read(idx, ctypes.byref(p))
     return p.as_dict()
+
+
+def set_bins(mdt: int, t_wave: int, t_block: int) -> None:
+    """Degree-bin parameters of 'binned' solves (see lbg_set_bins)."""
+    _check(lib.lbg_set_bins(ctypes.byref(Bins(int(mdt), int(t_wave), int(t_block)))))
+
+
+def get_bins() -> dict:
+    b = Bins()
+    lib.lbg_get_bins(ctypes.byref(b))
+    return b.as_dict()
+
+
+def degree_mdt(g: DeviceGraph, workspace: Workspace | None = None, stream=None) -> tuple:
+    """(MDT, max out-degree) of the graph by the histogram rule of Section
+    III-B, computed on the device (see lbg_degree_mdt)."""
+    ws = _ws(workspace, workspace_bytes(g.n, g.m, NODE, False), g.offsets.device)
+    mdt, mx = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib.lbg_degree_mdt(_ptr(g.offsets), g.n, g.m, _ptr(ws), ws.numel(), ctypes.byref(mdt),
+                              ctypes.byref(mx), _stream(stream)))
+    return mdt.value, mx.value
+
+
+def autotune_bins(g: DeviceGraph, sources, workspace: Workspace | None = None, stream=None) -> dict:
+    """Time 'binned' BFS (and SSSP if the graph has weights) from `sources`
+    over candidate bin parameters and keep the fastest (lbg_autotune_bins)."""
+    need = max(workspace_bytes(g.n, g.m, BINNED, False), workspace_bytes(g.n, g.m, BINNED, True))
+    ws = _ws(workspace, need, g.offsets.device)
+    src = (ctypes.c_int32 * len(sources))(*[int(x) for x in sources])
+    out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    best = Bins()
+    _check(lib.lbg_autotune_bins(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, src,
+                                 len(sources), _ptr(out), _ptr(ws), ws.numel(), ctypes.byref(best),
+                                 _stream(stream)))
+    return best.as_dict()
 
 
 def tile_edges() -> int:

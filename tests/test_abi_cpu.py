@@ -49,6 +49,10 @@ def test_workspace_formulas():
     # edge-based: two worklists of m arc ids (the COO-scale cost, Section II-B)
     assert lbgmod.workspace_bytes(n, m, "edge", False) == ctl + bfs_state + 2 * al(4 * m)
     assert lbgmod.workspace_bytes(n, m, "edge", True) == ctl + sssp_state + 2 * al(4 * m)
+    # binned: split hubs add at most m / 64 entries per level
+    cap = n + m // 64 + 1
+    exp_binned = ctl + bfs_state + 2 * (3 * al(4 * cap) + al(4 * tiles))
+    assert lbgmod.workspace_bytes(n, m, "binned", False) == exp_binned
     # CSR strategies stay O(n + m / tile); the edge one grows with m
     assert lbgmod.workspace_bytes(n, 50 * m, "balanced", False) < lbgmod.workspace_bytes(n, 50 * m, "edge", False) / 10
     # invalid arguments
@@ -134,3 +138,18 @@ def test_batch_workspace_and_argument_errors():
     assert solve([ok], n=0) == lbgmod.EINVAL
     assert lib.lbg_batch_solve(FAKE, FAKE, FAKE, 100, 50, None, 0, FAKE, 10, 10, WS, 1 << 40,
                                None, None) == lbgmod.EINVAL
+
+
+def test_bins_validation_and_round_trip():
+    saved = lbgmod.get_bins()
+    for bad in ((10, 8, 16), (-1, 8, 16), (128, 64, 32), (128, -1, 16)):
+        with pytest.raises(lbgmod.LbgError):
+            lbgmod.set_bins(*bad)
+    assert lbgmod.get_bins() == saved  # a rejected call changes nothing
+    lbgmod.set_bins(0, 8, 8)
+    assert lbgmod.get_bins() == {"mdt": 0, "t_wave": 8, "t_block": 8}
+    lbgmod.set_bins(**saved)
+    assert lbgmod.get_bins() == saved
+    out = ctypes.c_int32(0)
+    assert lib.lbg_degree_mdt(FAKE, 0, 5, WS, 1 << 20, ctypes.byref(out), None, None) == lbgmod.EINVAL
+    assert lib.lbg_degree_mdt(FAKE, 5, 5, WS, 8, ctypes.byref(out), None, None) == lbgmod.ENOMEM

@@ -16,7 +16,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 from paper_1711_00231_amd import lbg  # noqa: E402  (fails loudly if liblbg.so is missing)
 
-STRATS = ["node", "edge", "balanced"]
+STRATS = ["node", "edge", "balanced", "binned"]
 O = oracle.get()
 
 
@@ -154,6 +154,47 @@ def test_small_frontier_switching():
     # a chain long enough that almost every level runs on the device
     h = pins.path_graph(5000, np.arange(1, 5000) % 7)
     _check(h, _dev(h), [0, 2500], "balanced")
+
+
+def test_degree_mdt_matches_oracle():
+    """The device MDT (Section III-B histogram rule) equals the oracle's on
+    skewed, uniform and grid graphs (an integer: compared exactly)."""
+    for g in (graphgen.rmat(16, salt=3), graphgen.uniform(12, k=5, salt=4), graphgen.grid(70),
+              pins.path_graph(100, np.ones(99)), graphgen.from_edges(4, [], [], [], "no-arcs")):
+        mdt, mx = lbg.degree_mdt(_dev(g))
+        assert mx == int(g.degrees.max())
+        assert mdt == O.mdt(g.offsets)[0], g.name
+
+
+@pytest.mark.parametrize("bins", [(64, 0, 64), (64, 63, 64), (0, 8, 32), (16384, 64, 4096)])
+def test_binned_bin_parameters(bins):
+    """Results do not depend on the split size or the bin thresholds: heavy
+    splitting (every node above 64 arcs cut into pieces), all-wavefront,
+    no splitting, and coarse bins."""
+    saved = lbg.get_bins()
+    try:
+        lbg.set_bins(*bins)
+        g = graphgen.rmat(15)
+        _check(g, _dev(g), graphgen.sources(g, 2, graphgen.FAMILY_RMAT), "binned")
+        h = graphgen.uniform(13, k=9, salt=8)
+        _check(h, _dev(h), [0], "binned")
+    finally:
+        lbg.set_bins(**saved)
+
+
+def test_autotune_bins_keeps_results():
+    saved = lbg.get_bins()
+    try:
+        g = graphgen.rmat(14)
+        dg = _dev(g)
+        srcs = graphgen.sources(g, 2, graphgen.FAMILY_RMAT)
+        best = lbg.autotune_bins(dg, srcs)
+        assert best == lbg.get_bins()
+        assert best["mdt"] == 0 or best["mdt"] >= 64
+        assert 0 <= best["t_wave"] <= best["t_block"]
+        _check(g, dg, srcs, "binned")
+    finally:
+        lbg.set_bins(**saved)
 
 
 def test_repeat_runs_identical():
