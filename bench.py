@@ -258,6 +258,36 @@ def run_plain(args, lbg, torch, dev):
     return out, g, srcs
 
 
+# ----------------------------------------------------------- strategies --
+def run_strategies(lbg, torch, g, srcs, dev):
+    """Node-based vs edge-based vs balanced vs degree-binned assignment on the
+    same graph: BFS and SSSP from two sources each (binned with bins
+    autotuned on two other sources)."""
+    dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev, with_coo=True)
+    deg = g.degrees
+    tuned = lbg.autotune_bins(dg, [int(x) for x in srcs[2:4]])
+    ws = lbg.Workspace(dev)
+    out = {"bins": tuned}
+    for strat in ("node", "edge", "balanced", "binned"):
+        res = {}
+        for kind, f in (("bfs", lbg.bfs), ("sssp", lbg.sssp)):
+            ts, arcs = [], 0
+            for s in srcs[:2]:
+                lv = lbg.bfs(dg, int(s), strategy="balanced", workspace=ws).cpu().numpy()
+                arcs += int(deg[lv != lbg.BFS_INF].sum())
+                f(dg, int(s), strategy=strat, workspace=ws)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                f(dg, int(s), strategy=strat, workspace=ws)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            res[f"{kind}_ms"] = [round(x * 1e3, 3) for x in ts]
+            res[f"{kind}_gteps"] = round(arcs / sum(ts) / 1e9, 3)
+        out[strat] = res
+        log(f"strategy {strat}: {res}")
+    return out
+
+
 # -------------------------------------------------------------- batched --
 def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
     """The same 2 x sources x count queries solved as one batch and as
@@ -287,13 +317,20 @@ def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
         reached += int(deg[q[1]: q[2]][row != unreached].sum().item())
         off += q[2] - q[1]
     torch.cuda.synchronize()
-    tb = []
+    tb, tg = [], []
     for _ in range(reps):
         torch.cuda.synchronize()
         t = time.perf_counter()
         lbg.batch_solve(dg, queries, out=out, workspace=ws)
         torch.cuda.synchronize()
         tb.append(time.perf_counter() - t)
+    lbg.batch_solve(dg, queries, out=out, workspace=ws, graph=True)  # builds the graph
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lbg.batch_solve(dg, queries, out=out, workspace=ws, graph=True)
+        torch.cuda.synchronize()
+        tg.append(time.perf_counter() - t)
     # plain: one call per query on the query's own instance graph
     idx = np.searchsorted(nb, [q[0] for q in queries], side="right") - 1
     outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in gs]
@@ -310,11 +347,13 @@ def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
         lat.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t
-    bt = min(tb)
+    bt, gt = min(tb), min(tg)
     return {"queries": len(queries), "instances": count, "n": u.n, "m": u.m,
-            "batched_s": round(bt, 5), "plain_s": round(tp, 5),
-            "batched_gteps": round(reached / bt / 1e9, 4), "plain_gteps": round(reached / tp / 1e9, 4),
-            "speedup": round(tp / bt, 3),
+            "batched_s": round(bt, 5), "graph_batched_s": round(gt, 5), "plain_s": round(tp, 5),
+            "batched_gteps": round(reached / bt / 1e9, 4),
+            "graph_batched_gteps": round(reached / gt / 1e9, 4),
+            "plain_gteps": round(reached / tp / 1e9, 4),
+            "speedup": round(tp / bt, 3), "graph_speedup": round(tp / gt, 3),
             "plain_query_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
             "plain_query_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 4),
             "workload": f"{count} instances (half R-MAT scale U[10,{hi_exp}] ef 16 symmetrised, "
@@ -473,6 +512,8 @@ def main():
 
     out, g, srcs = run_plain(args, lbg, torch, dev)
     if not args.no_extras:
+        log("strategy comparison")
+        out["strategies"] = run_strategies(lbg, torch, g, srcs, dev)
         log("compact batched comparison")
         out["batched"] = run_batch(lbg, torch, dev, count=64, sources_per_instance=4, hi_exp=16)
         log("compact serving run")

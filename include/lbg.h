@@ -235,6 +235,20 @@ int lbg_batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t*
                     int64_t total_rows, int64_t total_arcs, void* workspace, size_t workspace_bytes,
                     lbg_stats* stats, void* stream);
 
+/* lbg_batch_solve with the level loop as a HIP graph: one instantiated graph
+ * runs 16 levels (the expansion reads its level from the control block), moves
+ * the level base on, writes the rows out once the worklist is empty and reads
+ * the control block back; the host replays it until the batch is done.  The
+ * executable graph is cached per host thread and reused while every argument
+ * stays the same (same buffers, sizes and queries' workspace layout); a call
+ * with other arguments rebuilds it.  Same arguments, results and errors as
+ * lbg_batch_solve.  For callers that launch many batches: the host issues one
+ * graph launch per 16 levels instead of 16 kernel launches. */
+int lbg_batch_solve_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
+                          int32_t n, int64_t m, const lbg_query* queries, int32_t num_queries,
+                          uint32_t* out, int64_t total_rows, int64_t total_arcs, void* workspace,
+                          size_t workspace_bytes, lbg_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------------
  * Engine: continuous batching for serving.  An engine keeps one packed graph
  * (as for lbg_batch_solve) and a pool of query slots; queries submitted

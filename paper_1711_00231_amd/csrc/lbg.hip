@@ -493,10 +493,91 @@ BatchLayout batch_layout(int32_t num_queries, int64_t rows, int64_t total_arcs) 
   return L;
 }
 
+// An instantiated graph of one replay of a graph-launched batch: kGraphLevels
+// expansion launches, the level advance, the conditional write-out and the
+// read-back of the control block.  Cached per thread and reused while the
+// launch arguments stay the same (they are copied into the graph).
+constexpr uint32_t kGraphLevels = 16;
+
+struct GraphCache {
+  std::vector<char> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void drop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+  }
+};
+thread_local GraphCache g_graph;  // not destroyed at exit: the runtime may be gone
+
+int batch_graph(const KArgs& a, bool narrow, int expand_blocks, dim3 rgrid, Ctl* host,
+                hipGraphExec_t* exec_out) {
+  std::vector<char> key(sizeof(KArgs) + 4 * sizeof(int64_t));
+  std::memcpy(key.data(), &a, sizeof(KArgs));
+  const int64_t extra[4] = {narrow ? 1 : 0, expand_blocks, static_cast<int64_t>(rgrid.x) << 32 | rgrid.y,
+                            static_cast<int64_t>(reinterpret_cast<uintptr_t>(host))};
+  std::memcpy(key.data() + sizeof(KArgs), extra, sizeof(extra));
+  if (g_graph.exec && g_graph.key == key) {
+    *exec_out = g_graph.exec;
+    return LBG_OK;
+  }
+  g_graph.drop();
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipGraphCreate(&g, 0));
+  g_graph.graph = g;
+  hipGraphNode_t prev = nullptr;
+  KArgs args = a;
+  auto add_kernel = [&](const void* fn, dim3 grid, void** params) -> int {
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(fn);
+    p.gridDim = grid;
+    p.blockDim = dim3(lbg::kBlock);
+    p.sharedMemBytes = 0;
+    p.kernelParams = params;
+    p.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    HIP_TRY(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+    prev = node;
+    return LBG_OK;
+  };
+  int rc;
+  const void* expand = narrow ? reinterpret_cast<const void*>(lbg::k_expand_batched_graph<true>)
+                              : reinterpret_cast<const void*>(lbg::k_expand_batched_graph<false>);
+  for (uint32_t k = 0; k < kGraphLevels; ++k) {
+    uint32_t kk = k;
+    void* params[] = {&args, &kk};
+    if ((rc = add_kernel(expand, dim3(expand_blocks), params)) != LBG_OK) return rc;
+  }
+  {
+    Ctl* ctl = args.ctl;
+    uint32_t K = kGraphLevels;
+    void* params[] = {&ctl, &K};
+    if ((rc = add_kernel(reinterpret_cast<const void*>(lbg::k_level_advance), dim3(1), params)) != LBG_OK)
+      return rc;
+  }
+  {
+    uint32_t L = 0xffffffffu;
+    void* params[] = {&args, &L};
+    if ((rc = add_kernel(reinterpret_cast<const void*>(lbg::k_batch_finish), rgrid, params)) != LBG_OK)
+      return rc;
+  }
+  hipGraphNode_t cp = nullptr;
+  HIP_TRY(hipGraphAddMemcpyNode1D(&cp, g, &prev, 1, host, args.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  hipGraphExec_t exec = nullptr;
+  HIP_TRY(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+  g_graph.exec = exec;
+  g_graph.key = key;
+  *exec_out = exec;
+  return LBG_OK;
+}
+
 int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
                 int64_t m, const lbg_query* queries, int32_t num_queries, uint32_t* out,
                 int64_t rows, int64_t total_arcs, void* workspace, size_t workspace_bytes,
-                lbg_stats* stats, hipStream_t st) {
+                lbg_stats* stats, hipStream_t st, bool use_graph) {
   if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
   if (m < 0 || m > INT32_MAX)
     return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
@@ -579,7 +660,21 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
   uint32_t L = 0, batch = 8;
   size_t nev = 0;
   const uint64_t level_cap = static_cast<uint64_t>(rows) + 2;
-  for (;;) {
+  if (use_graph) {
+    hipGraphExec_t exec = nullptr;
+    int rc = batch_graph(a, narrow, GR.multi[narrow ? 1 : 0], rgrid, host, &exec);
+    if (rc) return rc;
+    for (;;) {
+      HIP_TRY(hipGraphLaunch(exec, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (host->error)
+        return fail(LBG_EOVERFLOW, "device capacity/bounds guard tripped (flags 0x%x)", host->error);
+      L = host->level_base;
+      if (static_cast<uint32_t>(host->ctr[L % 3]) == 0u) break;
+      if (L > level_cap) return fail(LBG_EINTERNAL, "more levels than rows; malformed input?");
+    }
+  }
+  for (; !use_graph;) {
     for (uint32_t k = 0; k < batch; ++k, ++L) {
       if (profiling) {
         hipEvent_t e = event_at(nev++);
@@ -1108,7 +1203,17 @@ int lbg_batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t*
                     int64_t total_rows, int64_t total_arcs, void* workspace, size_t workspace_bytes,
                     lbg_stats* stats, void* stream) {
   return batch_solve(offsets, cols, weights, n, m, queries, num_queries, out, total_rows,
-                     total_arcs, workspace, workspace_bytes, stats, static_cast<hipStream_t>(stream));
+                     total_arcs, workspace, workspace_bytes, stats, static_cast<hipStream_t>(stream),
+                     false);
+}
+
+int lbg_batch_solve_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
+                          int32_t n, int64_t m, const lbg_query* queries, int32_t num_queries,
+                          uint32_t* out, int64_t total_rows, int64_t total_arcs, void* workspace,
+                          size_t workspace_bytes, lbg_stats* stats, void* stream) {
+  return batch_solve(offsets, cols, weights, n, m, queries, num_queries, out, total_rows,
+                     total_arcs, workspace, workspace_bytes, stats, static_cast<hipStream_t>(stream),
+                     true);
 }
 
 int32_t lbg_tile_edges(void) { return static_cast<int32_t>(lbg::kMinTile); }

@@ -57,7 +57,7 @@ struct Ctl {
   unsigned long long p_frontier_entries;  // the part of the two totals above
   unsigned long long p_edges_scanned;     // done by the small-frontier kernel
   unsigned int deg_max;       // lbg_degree_mdt
-  unsigned int pad2;
+  unsigned int level_base;    // graph-launched batches: first level of the next replay
   unsigned long long pad1[6];
   // [x][0] updates, [x][1] global atomics issued; [x][2], [x][3] the same for
   // levels run by the small-frontier kernel

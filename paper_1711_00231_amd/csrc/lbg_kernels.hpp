@@ -564,8 +564,8 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   add_stats(a, upd, atom);
 }
 
-template <bool kSssp, bool kNarrow, bool kMulti = false>
-__global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
+template <bool kSssp, bool kNarrow, bool kMulti>
+__device__ __forceinline__ void balanced_level(const KArgs& a, uint32_t L) {
   const unsigned long long c = level_begin(a, L);
   if (static_cast<uint32_t>(c) == 0u) return;
   if (!level_fits<kSssp, kMulti>(a, c)) {
@@ -573,6 +573,24 @@ __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L)
     return;
   }
   expand_level<kSssp, kNarrow, kMulti>(a, L, c);
+}
+
+template <bool kSssp, bool kNarrow, bool kMulti = false>
+__global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
+  balanced_level<kSssp, kNarrow, kMulti>(a, L);
+}
+
+// Graph-launched batches: one replay of a graph runs levels level_base + k
+// for k = 0 .. K-1, then k_level_advance moves level_base on by K, so the
+// same graph, its arguments fixed, serves every replay.
+template <bool kNarrow>
+__global__ __launch_bounds__(kBlock) void k_expand_batched_graph(KArgs a, uint32_t k) {
+  const uint32_t L = __hip_atomic_load(&a.ctl->level_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + k;
+  balanced_level<true, kNarrow, true>(a, L);
+}
+
+__global__ void k_level_advance(Ctl* ctl, uint32_t K) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->level_base += K;
 }
 
 // ------------------------------------------------ small frontiers (a8) ----
@@ -1180,6 +1198,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_fill(KArgs a) {
       a.ctl->ctr[0] = a.ctl->ctr[1] = a.ctl->ctr[2] = 0ull;
       a.ctl->error = 0u;
       a.ctl->levels = 0u;
+      a.ctl->level_base = 0u;
       a.ctl->frontier_entries = 0ull;
       a.ctl->edges_scanned = 0ull;
     }
@@ -1246,8 +1265,10 @@ __global__ __launch_bounds__(kBlock) void k_engine_finish(KArgs a, const int32_t
 }
 
 // Once worklist L is empty, each row is written out: SSSP rows as distances,
-// BFS rows as int32 levels (INT32_MAX for unreached).
+// BFS rows as int32 levels (INT32_MAX for unreached).  L = UINT32_MAX: the
+// level is ctl->level_base (graph-launched batches).
 __global__ __launch_bounds__(kBlock) void k_batch_finish(KArgs a, uint32_t L) {
+  if (L == 0xffffffffu) L = __hip_atomic_load(&a.ctl->level_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
   if (static_cast<uint32_t>(c) != 0u) return;

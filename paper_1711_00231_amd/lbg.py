@@ -89,6 +89,8 @@ def _load():
     lib.lbg_batch_solve.restype = ctypes.c_int
     lib.lbg_batch_solve.argtypes = [vp, vp, vp, i32, i64, ctypes.POINTER(Query), i32, vp, i64, i64,
                                     vp, sz, ctypes.POINTER(Stats), vp]
+    lib.lbg_batch_solve_graph.restype = ctypes.c_int
+    lib.lbg_batch_solve_graph.argtypes = lib.lbg_batch_solve.argtypes
     lib.lbg_engine_workspace_bytes.restype = sz
     lib.lbg_engine_workspace_bytes.argtypes = [i32, i64, i64]
     lib.lbg_engine_create.restype = ctypes.c_int
@@ -273,9 +275,11 @@ def batch_workspace_bytes(num_queries: int, total_rows: int, total_arcs: int) ->
 
 
 def batch_solve(g: DeviceGraph, queries, out: torch.Tensor | None = None, total_arcs=None,
-                workspace: Workspace | None = None, stats: bool = False, stream=None):
+                workspace: Workspace | None = None, stats: bool = False, stream=None,
+                graph: bool = False):
     """Solve many BFS (kind 0) / SSSP (kind 1) queries over a packed graph in
-    one level-synchronous batch (see lbg_batch_solve).  ``queries``: sequence
+    one level-synchronous batch (see lbg_batch_solve; graph=True replays a
+    cached HIP graph of 16 levels, lbg_batch_solve_graph).  ``queries``: sequence
     of (src, lo, hi, kind[, out_off]) with global node ids.  Returns the int32
     result tensor (BFS rows: levels; SSSP rows: uint32 bit patterns) or
     (tensor, stats)."""
@@ -294,7 +298,8 @@ def batch_solve(g: DeviceGraph, queries, out: torch.Tensor | None = None, total_
         raise LbgError(EINVAL, "invalid batch sizes")
     ws = _ws(workspace, need, g.offsets.device)
     st = Stats()
-    rc = lib.lbg_batch_solve(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, qarr,
+    fn = lib.lbg_batch_solve_graph if graph else lib.lbg_batch_solve
+    rc = fn(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, qarr,
                              len(qarr), _ptr(out), out.numel(), total_arcs, _ptr(ws), ws.numel(),
                              ctypes.byref(st) if stats else None, _stream(stream))
     _check(rc)

@@ -93,3 +93,44 @@ def test_batch_rejects_arc_leaving_instance():
     with pytest.raises(lbg.LbgError) as ei:
         lbg.batch_solve(dg, [(0, 0, 3, lbg.KIND_BFS), (3, 3, 6, lbg.KIND_BFS)])
     assert ei.value.code == lbg.EOVERFLOW
+
+
+def test_graph_launched_batch_replays():
+    """The graph-launched batch (a cached HIP graph of 16 levels, replayed
+    until the batch is done) gives the oracle's rows on every call: reused
+    with eager work and synchronisations in between, rebuilt for other
+    buffers, and agreeing with the eager batch, including batches longer
+    than one replay (a 300-node path needs 300 levels)."""
+    gs = _instances() + [pins.path_graph(300, np.arange(1, 300) % 5 + 1)]
+    u, nb, _ = graphgen.pack(gs)
+    dg = lbg.DeviceGraph.from_numpy(u.offsets, u.cols, u.weights)
+    rng = np.random.default_rng(17)
+    queries, expect = [], []
+    for i, g in enumerate(gs):
+        for s in rng.integers(0, g.n, 2):
+            for kind in (lbg.KIND_BFS, lbg.KIND_SSSP):
+                queries.append((int(nb[i] + s), int(nb[i]), int(nb[i + 1]), kind))
+                expect.append(_expected(g, int(s), kind))
+    ws = lbg.Workspace("cuda")
+    rows = sum(q[2] - q[1] for q in queries)
+    out = torch.empty(rows, dtype=torch.int32, device="cuda")
+    eager = lbg.batch_solve(dg, queries, workspace=ws).cpu().numpy()
+    for rep in range(4):
+        out.fill_(-9)
+        lbg.batch_solve(dg, queries, out=out, workspace=ws, graph=True)
+        got = out.cpu().numpy()
+        assert np.array_equal(got, eager), rep
+        off = 0
+        for q, e in zip(queries, expect):
+            assert np.array_equal(got[off: off + q[2] - q[1]], e), (rep, q)
+            off += q[2] - q[1]
+        lbg.bfs(dg, int(queries[0][0]), workspace=lbg.Workspace("cuda"))  # eager work in between
+        torch.cuda.synchronize()
+    # other buffers: the cached graph must not be reused
+    out2 = torch.empty(rows, dtype=torch.int32, device="cuda")
+    got2 = lbg.batch_solve(dg, queries[::-1], out=out2, workspace=lbg.Workspace("cuda"), graph=True)
+    got2 = got2.cpu().numpy()
+    off = 0
+    for q, e in zip(queries[::-1], expect[::-1]):
+        assert np.array_equal(got2[off: off + q[2] - q[1]], e), q
+        off += q[2] - q[1]
