@@ -25,6 +25,9 @@
  *                 splitting of Section III-B, applied to worklist entries),
  *                 and each entry is expanded by one lane, one wavefront or one
  *                 workgroup according to its length (lbg_set_bins)
+ *   LBG_EDGE_NOCHUNK  LBG_EDGE without work chunking: every arc of an
+ *                 improved node is reserved with its own atomic on the tail
+ *                 (the ablation of Section IV-D; slow by design)
  *   LBG_AUTO      currently LBG_BALANCED
  *
  * Conventions for every entry point
@@ -72,7 +75,8 @@ typedef enum {
   LBG_NODE = 1,
   LBG_EDGE = 2,
   LBG_BALANCED = 3,
-  LBG_BINNED = 4
+  LBG_BINNED = 4,
+  LBG_EDGE_NOCHUNK = 5
 } lbg_strategy;
 
 /* Counters of one solve (host struct, filled when `stats` is not NULL).
@@ -103,7 +107,8 @@ size_t lbg_workspace_bytes(int32_t n, int64_t m, int32_t strategy, int32_t is_ss
  * out-arcs, INT32_MAX if v is unreachable.  workspace: device buffer of at
  * least lbg_workspace_bytes(n, m, strategy, 0) bytes, 256-byte aligned, that
  * the call overwrites.  coo_src: device int32[m], the source node of every
- * arc in CSR order; required for LBG_EDGE, ignored otherwise (may be NULL). */
+ * arc in CSR order; required for LBG_EDGE and LBG_EDGE_NOCHUNK, ignored
+ * otherwise (may be NULL). */
 int lbg_bfs(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, int32_t src,
             int32_t* levels_out, void* workspace, size_t workspace_bytes, int32_t strategy,
             const int32_t* coo_src, lbg_stats* stats, void* stream);

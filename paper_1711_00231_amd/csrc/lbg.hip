@@ -39,7 +39,8 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_BINNED; }
+bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_EDGE_NOCHUNK; }
+bool edge_wl(int32_t s) { return s == LBG_EDGE || s == LBG_EDGE_NOCHUNK; }
 int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
 // Workspace layout.  All offsets 256-byte aligned.
@@ -68,7 +69,7 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
     L.seen[1] = take(sizeof(uint32_t) * words);
     L.xfilter = take(sizeof(uint32_t) * words * lbg::kXcds);
   }
-  if (s == LBG_EDGE) {
+  if (edge_wl(s)) {
     L.edge_cap = static_cast<uint32_t>(m);
     for (int b = 0; b < 2; ++b) L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(m > 0 ? m : 1));
   } else {
@@ -117,7 +118,7 @@ int resident_grid(K kernel) {
 }
 
 struct Grids {
-  int bal[2][2], node[2], edge[2], multi[2], binned[2];  // bal[is_sssp][narrow], multi[narrow]
+  int bal[2][2], node[2], edge[2], edge_nc[2], multi[2], binned[2];  // bal[is_sssp][narrow], multi[narrow]
   bool small[2][2];                                      // small-frontier kernel fits the device
 };
 
@@ -148,8 +149,10 @@ const Grids& grids() {
     g[dev].bal[1][1] = resident_grid(lbg::k_expand_balanced<true, true>);
     g[dev].node[0] = resident_grid(lbg::k_expand_node<false>);
     g[dev].node[1] = resident_grid(lbg::k_expand_node<true>);
-    g[dev].edge[0] = resident_grid(lbg::k_expand_edge<false>);
-    g[dev].edge[1] = resident_grid(lbg::k_expand_edge<true>);
+    g[dev].edge[0] = resident_grid(lbg::k_expand_edge<false, true>);
+    g[dev].edge[1] = resident_grid(lbg::k_expand_edge<true, true>);
+    g[dev].edge_nc[0] = resident_grid(lbg::k_expand_edge<false, false>);
+    g[dev].edge_nc[1] = resident_grid(lbg::k_expand_edge<true, false>);
     g[dev].binned[0] = resident_grid(lbg::k_expand_binned<false>);
     g[dev].binned[1] = resident_grid(lbg::k_expand_binned<true>);
     g[dev].multi[0] = resident_grid(lbg::k_expand_balanced<true, false, true>);
@@ -237,7 +240,7 @@ int check_common(const Problem& P) {
   if (!P.offsets || !P.out || !P.ws) return fail(LBG_EINVAL, "null offsets/output/workspace pointer");
   if (P.m > 0 && !P.cols) return fail(LBG_EINVAL, "null cols pointer with m > 0");
   if (P.is_sssp && P.m > 0 && !P.weights) return fail(LBG_EINVAL, "null weights pointer with m > 0");
-  if (resolve(P.strategy) == LBG_EDGE && !P.coo_src)
+  if (edge_wl(resolve(P.strategy)) && !P.coo_src)
     return fail(LBG_EINVAL, "LBG_EDGE needs the coo_src array");
   if (reinterpret_cast<uintptr_t>(P.ws) % kAlign)
     return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
@@ -272,7 +275,7 @@ int solve(const Problem& P) {
   }
   for (int b = 0; b < 2; ++b) {
     a.fr[b].node = reinterpret_cast<int32_t*>(ws + Lay.node[b]);
-    if (strat != LBG_EDGE) {
+    if (!edge_wl(strat)) {
       a.fr[b].eprefix = reinterpret_cast<uint32_t*>(ws + Lay.eprefix[b]);
       a.fr[b].estart = reinterpret_cast<int32_t*>(ws + Lay.estart[b]);
       a.fr[b].tile_node = reinterpret_cast<int32_t*>(ws + Lay.tile[b]);
@@ -311,10 +314,10 @@ int solve(const Problem& P) {
       std::min<int64_t>(std::max<int64_t>((static_cast<int64_t>(P.n) + lbg::kBlock - 1) / lbg::kBlock, 1), 4096));
 
   if (P.is_sssp) {
-    if (strat == LBG_EDGE) hipLaunchKernelGGL((lbg::k_init<true, true>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
+    if (edge_wl(strat)) hipLaunchKernelGGL((lbg::k_init<true, true>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
     else hipLaunchKernelGGL((lbg::k_init<true, false>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
   } else {
-    if (strat == LBG_EDGE) hipLaunchKernelGGL((lbg::k_init<false, true>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
+    if (edge_wl(strat)) hipLaunchKernelGGL((lbg::k_init<false, true>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
     else hipLaunchKernelGGL((lbg::k_init<false, false>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
   }
   HIP_TRY(hipGetLastError());
@@ -323,7 +326,8 @@ int solve(const Problem& P) {
     if (P.is_sssp) {
       switch (strat) {
         case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<true>), dim3(GR.node[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
-        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<true, true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_EDGE_NOCHUNK: hipLaunchKernelGGL((lbg::k_expand_edge<true, false>), dim3(GR.edge_nc[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<true>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         default:
           if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
@@ -333,7 +337,8 @@ int solve(const Problem& P) {
     } else {
       switch (strat) {
         case LBG_NODE: hipLaunchKernelGGL((lbg::k_expand_node<false>), dim3(GR.node[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
-        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<false>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<false, true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_EDGE_NOCHUNK: hipLaunchKernelGGL((lbg::k_expand_edge<false, false>), dim3(GR.edge_nc[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<false>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         default:
           if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<false, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);

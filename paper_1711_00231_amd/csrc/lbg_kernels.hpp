@@ -1102,7 +1102,10 @@ __global__ __launch_bounds__(kBlock) void k_expand_binned(KArgs a, uint32_t L) {
 // the grid-stride loop relaxes arc wl[i] (SSSP reads its source from the COO
 // array); a node whose value improved pushes all of its arcs, reserved with
 // one atomic per wave batch (work chunking).
-template <bool kSssp>
+//
+// kChunk = false is the ablation without work chunking (Section IV-D): an
+// improved node reserves each of its arcs with its own atomic on the tail.
+template <bool kSssp, bool kChunk>
 __global__ __launch_bounds__(kBlock) void k_expand_edge(KArgs a, uint32_t L) {
   __shared__ int32_t qS[kWaves][kQueue];
   __shared__ int32_t qD[kWaves][kQueue];
@@ -1138,7 +1141,15 @@ __global__ __launch_bounds__(kBlock) void k_expand_edge(KArgs a, uint32_t L) {
       }
       want = relax<kSssp>(a, L, v, du, w, &upd, &atom, &s, &d);
     }
-    q.push(want, s, d, 0, flush);
+    if (kChunk) {
+      q.push(want, s, d, 0, flush);
+    } else if (want) {
+      for (int32_t t = 0; t < d; ++t) {
+        const uint32_t p = static_cast<uint32_t>(atomicAdd(&a.ctl->ctr[nctr], 1ull));
+        if (p < a.edge_cap) nwl[p] = s + t;
+        else atomicOr(&a.ctl->error, kErrEdgeCap);
+      }
+    }
   }
   flush();
   add_stats(a, upd, atom);

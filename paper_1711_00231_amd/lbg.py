@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbg.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
-AUTO, NODE, EDGE, BALANCED, BINNED = 0, 1, 2, 3, 4
-STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED, "binned": BINNED}
+AUTO, NODE, EDGE, BALANCED, BINNED, EDGE_NOCHUNK = 0, 1, 2, 3, 4, 5
+STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED, "binned": BINNED,
+              "edge_nochunk": EDGE_NOCHUNK}
 BFS_INF = 2**31 - 1
 SSSP_INF = 2**32 - 1
 
@@ -229,7 +230,7 @@ def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None 
         out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
     need = workspace_bytes(g.n, g.m, s, False)
     ws = _ws(workspace, need, g.offsets.device)
-    coo = g.ensure_coo() if s == EDGE else None
+    coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
     rc = lib.lbg_bfs(_ptr(g.offsets), _ptr(g.cols), g.n, g.m, int(src), _ptr(out), _ptr(ws),
                      ws.numel(), s, _ptr(coo), ctypes.byref(st) if stats else None, _stream(stream))
@@ -248,7 +249,7 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
         out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
     need = workspace_bytes(g.n, g.m, s, True)
     ws = _ws(workspace, need, g.offsets.device)
-    coo = g.ensure_coo() if s == EDGE else None
+    coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
     rc = lib.lbg_sssp(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(src),
                       _ptr(out), _ptr(ws), ws.numel(), s, _ptr(coo),

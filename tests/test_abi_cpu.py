@@ -49,6 +49,7 @@ def test_workspace_formulas():
     # edge-based: two worklists of m arc ids (the COO-scale cost, Section II-B)
     assert lbgmod.workspace_bytes(n, m, "edge", False) == ctl + bfs_state + 2 * al(4 * m)
     assert lbgmod.workspace_bytes(n, m, "edge", True) == ctl + sssp_state + 2 * al(4 * m)
+    assert lbgmod.workspace_bytes(n, m, "edge_nochunk", True) == ctl + sssp_state + 2 * al(4 * m)
     # binned: split hubs add at most m / 64 entries per level
     cap = n + m // 64 + 1
     exp_binned = ctl + bfs_state + 2 * (3 * al(4 * cap) + al(4 * tiles))
@@ -87,6 +88,7 @@ def _sssp(n=10, m=20, src=0, weights=FAKE, strategy=lbgmod.BALANCED, coo=None, w
     (dict(ws=None), lbgmod.EINVAL),
     (dict(cols=None), lbgmod.EINVAL),
     (dict(strategy=7), lbgmod.EINVAL),
+    (dict(strategy=lbgmod.EDGE_NOCHUNK), lbgmod.EINVAL),  # no coo_src
     (dict(strategy=lbgmod.EDGE), lbgmod.EINVAL),          # no coo_src
     (dict(ws=ctypes.c_void_p(0x10010)), lbgmod.EINVAL),  # misaligned workspace
     (dict(ws_bytes=100), lbgmod.ENOMEM),
