@@ -35,10 +35,11 @@
  *     non-decreasing, offsets[n] = m), cols[m] int32 in [0, n), weights[m]
  *     uint32.  Duplicate arcs and self-loops are allowed.
  *   - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA
- *     tensors), except `stats` (host).  The caller owns every buffer; the
- *     library allocates no device memory and keeps no state between calls
- *     other than process-wide profiling counters and one small pinned host
- *     word per thread.
+ *     tensors), except `stats` and the batched query table (host).  The
+ *     caller owns every buffer; the library allocates no device memory.  It
+ *     keeps, between calls: process-wide profiling counters and degree-bin
+ *     parameters, per-device launch sizes, and per host thread one pinned
+ *     control-block copy, its event pool and the last batch graph.
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
  *     work is ordered on it.  The call returns after the solve has finished
  *     on the stream (the level loop reads the frontier size back to decide
@@ -47,7 +48,8 @@
  *     then returns a negative lbg_status, outputs are untouched and
  *     lbg_last_error() describes the problem.  A full structural check of the
  *     CSR is O(n + m) and therefore opt-in: lbg_validate_csr().
- *   - Thread safety: concurrent calls are safe on distinct workspaces.
+ *   - Thread safety: concurrent calls are safe on distinct workspaces (and
+ *     output buffers); lbg_set_bins affects binned solves that start later.
  */
 #ifndef LBG_H
 #define LBG_H
