@@ -170,7 +170,7 @@ int grid_blocks() { return grids().bal[0][1]; }
 
 // Degree-bin parameters of LBG_BINNED solves (process-wide; lbg_set_bins).
 std::mutex g_bins_mu;
-lbg_bins g_bins{4096, 32, 1024};
+lbg_bins g_bins{256, 16, 1024};  // what the autotuner picks on R-MAT scale 22
 
 // Host side of the profiling counters (see lbg_profile_enable).
 std::mutex g_prof_mu;

@@ -12,11 +12,12 @@
 // reads), so each path filters with plain reads before it issues one:
 //  * BFS claims an undiscovered node with an atomic OR on a visited bitmap.
 //    An atomic on a line invalidates that line in every XCD's L2, so the hot
-//    path never reads the bitmap it claims through: it reads `seen`, a copy
-//    frozen for the level (nodes visited before level L; n/8 bytes, resident
-//    in every L2), then a per-XCD advisory copy that the XCD's own claimants
-//    update with plain stores, so an XCD issues about one atomic per new
-//    node.  The winner writes level L+1 and sets the bit in next level's
+//    path never reads the bitmap it claims through.  It reads one per-XCD
+//    advisory filter (n/8 bytes, resident in the XCD's L2) that holds `seen`
+//    (a copy of the bitmap frozen for the level, merged in when the level
+//    starts) plus the claims of the XCD's own blocks (plain stores), so a
+//    visited node costs one L2 read and an XCD issues about one atomic per
+//    new node.  The winner writes level L+1 and sets the bit in next level's
 //    `seen`, which this launch also refreshes from the current one (plain
 //    stores; a bit lost to a racing store only costs one more atomic later).
 //  * SSSP keeps (distance << 32 | iteration of last improvement) per node and
@@ -71,12 +72,22 @@ __device__ __forceinline__ unsigned long long level_begin(const KArgs& a, uint32
   return c;
 }
 
-// BFS: next level's `seen` snapshot starts as this level's (whole grid).
+// BFS, at the start of level L: the next level's `seen` snapshot starts as
+// this level's (whole grid), and each XCD's advisory filter absorbs this
+// level's snapshot (by the XCD's own blocks), so one read of the filter
+// answers both "visited before this level" and "claimed by this XCD".
+// Plain read-modify-writes: a bit lost to a racing store costs one atomic.
 __device__ __forceinline__ void refresh_seen(const KArgs& a, uint32_t L) {
   const uint32_t* cur = a.seen[L & 1];
   uint32_t* nxt = a.seen[(L + 1) & 1];
   for (uint32_t k = blockIdx.x * kBlock + threadIdx.x; k < a.words; k += gridDim.x * kBlock)
     nxt[k] = cur[k];
+  uint32_t* fx = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
+  const uint32_t xb = blockIdx.x / kXcds, nxb = (gridDim.x - blockIdx.x % kXcds + kXcds - 1) / kXcds;
+  for (uint32_t k = xb * kBlock + threadIdx.x; k < a.words; k += nxb * kBlock) {
+    const uint32_t sw = cur[k];
+    if (sw) fx[k] |= sw;
+  }
 }
 
 // Block-level reduction of the per-thread counters, then one atomic per
@@ -117,8 +128,7 @@ __device__ __forceinline__ bool relax(const KArgs& a, uint32_t L, int32_t v, uin
   if (!kSssp) {
     const uint32_t word = static_cast<uint32_t>(v) >> 5;
     const uint32_t bit = 1u << (v & 31);
-    if (a.seen[L & 1][word] & bit) return false;
-    uint32_t* f = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
+    uint32_t* f = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;  // holds `seen`
     const uint32_t fw = f[word];
     if (fw & bit) return false;  // this XCD already claimed (or is claiming) v
     f[word] = fw | bit;          // plain store; a lost bit only costs one more atomic
@@ -296,7 +306,6 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   const uint32_t wid = threadIdx.x >> 6;
   WaveLds<kSssp, kMulti>& w = lds[wid];
   uint32_t* fx = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
-  const uint32_t* seen_cur = a.seen[L & 1];
   uint32_t* seen_nxt = a.seen[(L + 1) & 1];
   // A frontier node's own distance comes from the packed state
   // (authoritative); the per-arc filter reads the output array.
@@ -442,14 +451,12 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
     }
     bool push[kItems];
     if (!kSssp) {
-      // Phase B: frozen visited snapshot; phase C: this XCD's advisory
-      // filter; phase D: one atomic per surviving candidate.
+      // Phase B: this XCD's advisory filter, which holds the frozen visited
+      // snapshot (merged in at level start) and the XCD's own claims: one
+      // random read per arc; phase C: one atomic per surviving candidate.
       uint32_t x[kItems];
 #pragma unroll
-      for (int r = 0; r < kItems; ++r) x[r] = vv[r] >= 0 ? *at<kNarrow>(seen_cur, static_cast<uint32_t>(vv[r]) >> 5) : ~0u;
-#pragma unroll
-      for (int r = 0; r < kItems; ++r)
-        x[r] = (vv[r] >= 0 && !(x[r] & (1u << (vv[r] & 31)))) ? *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) : ~0u;
+      for (int r = 0; r < kItems; ++r) x[r] = vv[r] >= 0 ? *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) : ~0u;
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t bit = 1u << (vv[r] & 31);
