@@ -260,7 +260,8 @@ def run_plain(args, lbg, torch, dev):
 
 # ----------------------------------------------------------- strategies --
 def run_strategies(lbg, torch, g, srcs, dev):
-    """Node-based vs edge-based vs balanced vs degree-binned assignment on the
+    """Node-based vs edge-based vs hierarchical vs balanced vs degree-binned
+    assignment on the
     same graph: BFS and SSSP from two sources each (binned with bins
     autotuned on two other sources)."""
     dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev, with_coo=True)
@@ -268,7 +269,7 @@ def run_strategies(lbg, torch, g, srcs, dev):
     tuned = lbg.autotune_bins(dg, [int(x) for x in srcs[2:4]])
     ws = lbg.Workspace(dev)
     out = {"bins": tuned}
-    for strat in ("node", "edge", "balanced", "binned"):
+    for strat in ("node", "edge", "hier", "balanced", "binned"):
         res = {}
         for kind, f in (("bfs", lbg.bfs), ("sssp", lbg.sssp)):
             ts, arcs = [], 0

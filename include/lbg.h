@@ -25,6 +25,12 @@
  *                 splitting of Section III-B, applied to worklist entries),
  *                 and each entry is expanded by one lane, one wavefront or one
  *                 workgroup according to its length (lbg_set_bins)
+ *   LBG_HIER      hierarchical processing (Section III-C): sub-iteration s
+ *                 of a level relaxes arcs [s*MDT, (s+1)*MDT) of each frontier
+ *                 node still active, one thread per node, MDT by the
+ *                 histogram rule (lbg_degree_mdt); once fewer than 1024
+ *                 nodes remain active their remaining arcs are expanded
+ *                 edge-balanced
  *   LBG_EDGE_NOCHUNK  LBG_EDGE without work chunking: every arc of an
  *                 improved node is reserved with its own atomic on the tail
  *                 (the ablation of Section IV-D; slow by design)
@@ -78,7 +84,8 @@ typedef enum {
   LBG_EDGE = 2,
   LBG_BALANCED = 3,
   LBG_BINNED = 4,
-  LBG_EDGE_NOCHUNK = 5
+  LBG_EDGE_NOCHUNK = 5,
+  LBG_HIER = 6
 } lbg_strategy;
 
 /* Counters of one solve (host struct, filled when `stats` is not NULL).

@@ -39,13 +39,13 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_EDGE_NOCHUNK; }
+bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_HIER; }
 bool edge_wl(int32_t s) { return s == LBG_EDGE || s == LBG_EDGE_NOCHUNK; }
 int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
 // Workspace layout.  All offsets 256-byte aligned.
 struct Layout {
-  size_t ctl, visited, seen[2], xfilter, dstate, d16, node[2], eprefix[2], estart[2], tile[2], total;
+  size_t ctl, visited, seen[2], xfilter, dstate, d16, node[2], eprefix[2], estart[2], tile[2], sub[2], total;
   uint32_t node_cap, tile_cap, edge_cap;
 };
 
@@ -81,6 +81,7 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
       L.eprefix[b] = take(sizeof(uint32_t) * static_cast<size_t>(L.node_cap));
       L.estart[b] = take(sizeof(int32_t) * static_cast<size_t>(L.node_cap));
       L.tile[b] = take(sizeof(int32_t) * static_cast<size_t>(L.tile_cap));
+      if (s == LBG_HIER) L.sub[b] = take(sizeof(int32_t) * static_cast<size_t>(n));
     }
   }
   L.total = off;
@@ -118,7 +119,7 @@ int resident_grid(K kernel) {
 }
 
 struct Grids {
-  int bal[2][2], node[2], edge[2], edge_nc[2], multi[2], binned[2];  // bal[is_sssp][narrow], multi[narrow]
+  int bal[2][2], node[2], edge[2], edge_nc[2], multi[2], binned[2], hier[2];  // bal[is_sssp][narrow], multi[narrow]
   bool small[2][2];                                      // small-frontier kernel fits the device
 };
 
@@ -153,6 +154,8 @@ const Grids& grids() {
     g[dev].edge[1] = resident_grid(lbg::k_expand_edge<true, true>);
     g[dev].edge_nc[0] = resident_grid(lbg::k_expand_edge<false, false>);
     g[dev].edge_nc[1] = resident_grid(lbg::k_expand_edge<true, false>);
+    g[dev].hier[0] = resident_grid(lbg::k_expand_hier<false>);
+    g[dev].hier[1] = resident_grid(lbg::k_expand_hier<true>);
     g[dev].binned[0] = resident_grid(lbg::k_expand_binned<false>);
     g[dev].binned[1] = resident_grid(lbg::k_expand_binned<true>);
     g[dev].multi[0] = resident_grid(lbg::k_expand_balanced<true, false, true>);
@@ -212,6 +215,22 @@ int64_t xsum(const Ctl* c, int k) {
   int64_t t = 0;
   for (int x = 0; x < lbg::kXcds; ++x) t += static_cast<int64_t>(c->xstat[x][k]);
   return t;
+}
+
+// MDT of Section III-B from the degree histogram the k_deg_* kernels left in
+// the control block: k = the fullest bin (ties to the smaller, bins numbered
+// from 1), MDT = max(1, floor(k * maxDegree / bins)).
+uint32_t mdt_rule(const Ctl* c) {
+  int best = 1;
+  int64_t best_count = -1;
+  for (int b = 1; b <= lbg::kMdtBins; ++b) {
+    const int64_t cnt = xsum(c, b - 1);
+    if (cnt > best_count) {
+      best_count = cnt;
+      best = b;
+    }
+  }
+  return static_cast<uint32_t>(std::max<int64_t>(1, best * static_cast<int64_t>(c->deg_max) / lbg::kMdtBins));
 }
 
 struct Problem {
@@ -280,6 +299,7 @@ int solve(const Problem& P) {
       a.fr[b].estart = reinterpret_cast<int32_t*>(ws + Lay.estart[b]);
       a.fr[b].tile_node = reinterpret_cast<int32_t*>(ws + Lay.tile[b]);
     }
+    if (strat == LBG_HIER) a.sub[b] = reinterpret_cast<int32_t*>(ws + Lay.sub[b]);
   }
   a.ctl = reinterpret_cast<Ctl*>(ws + Lay.ctl);
   a.n = static_cast<uint32_t>(P.n);
@@ -313,6 +333,21 @@ int solve(const Problem& P) {
   const int init_blocks = static_cast<int>(
       std::min<int64_t>(std::max<int64_t>((static_cast<int64_t>(P.n) + lbg::kBlock - 1) / lbg::kBlock, 1), 4096));
 
+  // hierarchical strategy: MDT and the number of sub-iterations per level
+  // from the degree histogram (one read-back per solve)
+  uint32_t hier_mdt = 1, hier_subs = 1;
+  if (strat == LBG_HIER) {
+    hipLaunchKernelGGL(lbg::k_deg_clear, dim3(1), dim3(lbg::kBlock), 0, st, a.ctl);
+    hipLaunchKernelGGL(lbg::k_deg_max, dim3(init_blocks), dim3(lbg::kBlock), 0, st, P.offsets, a.n, a.ctl);
+    hipLaunchKernelGGL(lbg::k_deg_hist, dim3(init_blocks), dim3(lbg::kBlock), 0, st, P.offsets, a.n, a.ctl);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const uint32_t mx = host->deg_max;
+    hier_mdt = mdt_rule(host);
+    hier_subs = std::max<uint32_t>(1, (mx + hier_mdt - 1) / hier_mdt);
+  }
+
   if (P.is_sssp) {
     if (edge_wl(strat)) hipLaunchKernelGGL((lbg::k_init<true, true>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
     else hipLaunchKernelGGL((lbg::k_init<true, false>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
@@ -329,6 +364,11 @@ int solve(const Problem& P) {
         case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<true, true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_EDGE_NOCHUNK: hipLaunchKernelGGL((lbg::k_expand_edge<true, false>), dim3(GR.edge_nc[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<true>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_HIER:
+          hipLaunchKernelGGL(lbg::k_hier_reset, dim3(1), dim3(64), 0, st, a.ctl);
+          for (uint32_t k = 0; k < hier_subs; ++k)
+            hipLaunchKernelGGL((lbg::k_expand_hier<true>), dim3(GR.hier[sv]), dim3(lbg::kBlock), 0, st, a, L, k, hier_mdt);
+          break;
         default:
           if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
           else hipLaunchKernelGGL((lbg::k_expand_balanced<true, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
@@ -340,6 +380,11 @@ int solve(const Problem& P) {
         case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<false, true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_EDGE_NOCHUNK: hipLaunchKernelGGL((lbg::k_expand_edge<false, false>), dim3(GR.edge_nc[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<false>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_HIER:
+          hipLaunchKernelGGL(lbg::k_hier_reset, dim3(1), dim3(64), 0, st, a.ctl);
+          for (uint32_t k = 0; k < hier_subs; ++k)
+            hipLaunchKernelGGL((lbg::k_expand_hier<false>), dim3(GR.hier[sv]), dim3(lbg::kBlock), 0, st, a, L, k, hier_mdt);
+          break;
         default:
           if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<false, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
           else hipLaunchKernelGGL((lbg::k_expand_balanced<false, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
@@ -1115,18 +1160,8 @@ int lbg_degree_mdt(const int32_t* offsets, int32_t n, int64_t m, void* workspace
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(host, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const int64_t mx = host->deg_max;
-  int best = 1;
-  int64_t best_count = -1;
-  for (int b = 1; b <= lbg::kMdtBins; ++b) {
-    const int64_t cnt = xsum(host, b - 1);
-    if (cnt > best_count) {  // strictly greater: ties go to the smaller bin
-      best_count = cnt;
-      best = b;
-    }
-  }
-  *mdt_out = static_cast<int32_t>(std::max<int64_t>(1, best * mx / lbg::kMdtBins));
-  if (max_degree_out) *max_degree_out = static_cast<int32_t>(mx);
+  *mdt_out = static_cast<int32_t>(mdt_rule(host));
+  if (max_degree_out) *max_degree_out = static_cast<int32_t>(host->deg_max);
   return LBG_OK;
 }
 

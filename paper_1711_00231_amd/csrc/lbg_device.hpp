@@ -58,7 +58,9 @@ struct Ctl {
   unsigned long long p_edges_scanned;     // done by the small-frontier kernel
   unsigned int deg_max;       // lbg_degree_mdt
   unsigned int level_base;    // graph-launched batches: first level of the next replay
-  unsigned long long pad1[6];
+  unsigned int sub_cnt[3];    // hierarchical strategy: sublist sizes of three sub-iterations
+  unsigned int pad3;
+  unsigned long long pad1[4];
   // [x][0] updates, [x][1] global atomics issued; [x][2], [x][3] the same for
   // levels run by the small-frontier kernel
   unsigned long long xstat[kXcds][16];
@@ -94,6 +96,7 @@ struct KArgs {
   unsigned long long* dstate;  // SSSP: (distance << 32) | iteration of last improvement
   uint16_t* d16;         // SSSP single solves: filter, min(an upper bound of the distance, 0xffff)
   Frontier fr[2];
+  int32_t* sub[2];       // hierarchical strategy: sublists (worklist indices) of two sub-iterations
   Ctl* ctl;
   uint32_t n;
   uint32_t m;

@@ -1104,6 +1104,177 @@ __global__ __launch_bounds__(kBlock) void k_expand_binned(KArgs a, uint32_t L) {
   add_stats(a, upd, atom);
 }
 
+// -------------------------------------------------- hierarchical (HP) ----
+// Hierarchical processing (Section III-C).  Sub-iteration s of a level
+// relaxes window [s * mdt, (s + 1) * mdt) of the arcs of every frontier
+// node still active, one thread per node; nodes with arcs beyond the window
+// form the sublist of sub-iteration s + 1 (appended with one atomic per
+// wavefront).  Once a sublist holds fewer than kHierWd nodes, its remaining
+// arcs are expanded edge-balanced instead (the hand-over to workload
+// decomposition): every block stages the sublist's remaining ranges and
+// their prefix in LDS and takes a grid-strided share of the arcs.  The host
+// enqueues ceil(maxDegree / mdt) sub-iterations per level; later ones find
+// an empty sublist and return.  Sublist counters rotate over three slots:
+// sub-iteration s reads sub_cnt[s % 3], appends to sub_cnt[(s + 1) % 3] and
+// clears sub_cnt[(s + 2) % 3]; k_hier_reset clears slot 1 before a level.
+constexpr uint32_t kHierWd = 1024;
+
+__global__ void k_hier_reset(Ctl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->sub_cnt[1] = 0u;
+}
+
+template <bool kSssp>
+__global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uint32_t sub, uint32_t mdt) {
+  __shared__ int32_t qS[kWaves][kQueue];
+  __shared__ int32_t qD[kWaves][kQueue];
+  __shared__ int32_t qV[kSssp ? kWaves : 1][kQueue];
+  __shared__ uint32_t ws_start[kHierWd], ws_pre[kHierWd], ws_du[kSssp ? kHierWd : 1];
+  __shared__ uint32_t wsum[kWaves];
+
+  unsigned long long c;
+  if (sub == 0) {
+    c = level_begin(a, L);
+  } else {
+    c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  const uint32_t Ef = static_cast<uint32_t>(c);
+  const uint32_t nf = static_cast<uint32_t>(c >> 32);
+  if (Ef == 0) return;
+  if (nf > a.node_cap || Ef > a.m) {
+    if (threadIdx.x == 0 && sub == 0) atomicOr(&a.ctl->error, kErrNodeCap);
+    return;
+  }
+  const uint32_t cnt = sub == 0 ? nf
+                                : __hip_atomic_load(&a.ctl->sub_cnt[sub % 3], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->sub_cnt[(sub + 2) % 3] = 0u;
+  if (cnt == 0) return;
+  if (!kSssp && sub == 0) refresh_seen(a, L);
+  const Frontier cur = a.fr[L & 1];
+  const Frontier nxt = a.fr[(L + 1) & 1];
+  const int32_t* in = sub == 0 ? nullptr : a.sub[(sub - 1) & 1];
+  int32_t* out = a.sub[sub & 1];
+  const int nctr = (L + 1) % 3;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  WaveQueue<kSssp> q{qS[wid], qD[wid], qV[kSssp ? wid : 0], 0u};
+  auto flush = [&]() { q.template flush_nodes<false>(a, nxt, nctr); };
+  uint32_t upd = 0, atom = 0;
+  const unsigned long long w0 = static_cast<unsigned long long>(sub) * mdt;
+
+  // entry e of the level: first arc, degree and (SSSP) current distance;
+  // deg = 0 when it was improved again this iteration (relaxed next time)
+  auto entry = [&](uint32_t e, uint32_t* st, uint32_t* deg, uint32_t* du) {
+    const uint32_t p = cur.eprefix[e];
+    const uint32_t pn = (e + 1 < nf) ? cur.eprefix[e + 1] : Ef;
+    *st = static_cast<uint32_t>(cur.estart[e]);
+    *deg = pn - p;
+    if (static_cast<unsigned long long>(*st) + *deg > a.m) {
+      atomicOr(&a.ctl->error, kErrBadArc);
+      *deg = 0;
+    }
+    *du = 0;
+    if (kSssp) {
+      const unsigned long long sv = a.dstate[cur.node[e]];
+      if (static_cast<uint32_t>(sv) == L + 1) *deg = 0;
+      *du = static_cast<uint32_t>(sv >> 32);
+    }
+  };
+  auto relax_push = [&](bool act, uint32_t arc, uint32_t du) {
+    int32_t v = -1, ns = 0, nd = 0;
+    bool want = false;
+    if (act) {
+      v = a.cols[arc];
+      want = relax<kSssp>(a, L, v, du, kSssp ? a.weights[arc] : 0u, &upd, &atom, &ns, &nd);
+    }
+    q.push(want, ns, nd, v, flush);
+  };
+
+  if (cnt >= kHierWd) {
+    // one thread per active node: this sub-iteration's window of its arcs
+    for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
+      const uint32_t i = base + tid;
+      uint32_t st = 0, deg = 0, du = 0;
+      if (i < cnt) entry(sub == 0 ? i : static_cast<uint32_t>(in[i]), &st, &deg, &du);
+      const unsigned long long lo = w0 < deg ? w0 : deg;
+      const unsigned long long hi = (w0 + mdt) < deg ? (w0 + mdt) : deg;
+      const uint32_t len = static_cast<uint32_t>(hi - lo);
+      const uint32_t rounds = static_cast<uint32_t>(wave_max(static_cast<int32_t>(len)));
+      for (uint32_t k = 0; k < rounds; ++k) relax_push(k < len, st + static_cast<uint32_t>(lo) + k, du);
+      // arcs beyond the window: the node stays active
+      const bool more = i < cnt && deg > w0 + mdt;
+      const uint64_t mask = __ballot(more);
+      if (mask) {
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(&a.ctl->sub_cnt[(sub + 1) % 3], static_cast<uint32_t>(__popcll(mask)));
+        b = __shfl(b, 0, 64);
+        if (more) {
+          const uint32_t k = b + lane_rank(mask);
+          if (k < a.node_cap) out[k] = static_cast<int32_t>(sub == 0 ? i : static_cast<uint32_t>(in[i]));
+          else atomicOr(&a.ctl->error, kErrNodeCap);
+        }
+      }
+    }
+  } else {
+    // hand-over: all remaining arcs of the (< kHierWd) active nodes, balanced
+    uint32_t st = 0, deg = 0, du = 0;
+    for (uint32_t j = tid; j < kHierWd; j += kBlock) {
+      uint32_t rem = 0, s0 = 0, d0 = 0;
+      if (j < cnt) {
+        entry(sub == 0 ? j : static_cast<uint32_t>(in[j]), &st, &deg, &du);
+        rem = deg > w0 ? static_cast<uint32_t>(deg - w0) : 0u;
+        s0 = st + static_cast<uint32_t>(deg > w0 ? w0 : deg);
+        d0 = du;
+      }
+      ws_start[j] = s0;
+      ws_pre[j] = rem;  // lengths for now, prefix below
+      if (kSssp) ws_du[j] = d0;
+    }
+    __syncthreads();
+    // exclusive prefix of the kHierWd lengths (4 per thread)
+    uint32_t v[kHierWd / kBlock], tsum = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kHierWd / kBlock; ++r) {
+      v[r] = ws_pre[tid * (kHierWd / kBlock) + r];
+      tsum += v[r];
+    }
+    const uint32_t inc = wave_incl_scan(tsum);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t before = inc - tsum, total = 0;
+    for (uint32_t w = 0; w < kWaves; ++w) {
+      if (w < wid) before += wsum[w];
+      total += wsum[w];
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < kHierWd / kBlock; ++r) {
+      ws_pre[tid * (kHierWd / kBlock) + r] = before;
+      before += v[r];
+    }
+    __syncthreads();
+    const uint32_t ne = cnt;  // entries with a range (zero lengths are skipped by the search)
+    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t rounds = (total + stride - 1) / stride;
+    for (uint32_t r = 0; r < rounds; ++r) {
+      const uint32_t e = r * stride + blockIdx.x * kBlock + tid;
+      bool act = e < total;
+      uint32_t arc = 0, d = 0;
+      if (act) {
+        uint32_t lo = 0, hi = ne;  // last entry with prefix <= e
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (ws_pre[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+        arc = ws_start[lo] + (e - ws_pre[lo]);
+        d = kSssp ? ws_du[lo] : 0u;
+      }
+      relax_push(act, arc, d);
+    }
+  }
+  flush();
+  add_stats(a, upd, atom);
+}
+
 // ---------------------------------------------------------- edge (EP) ----
 // Edge-based baseline (Section II-B): the worklist holds arc ids; thread i of
 // the grid-stride loop relaxes arc wl[i] (SSSP reads its source from the COO

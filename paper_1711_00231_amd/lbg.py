@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbg.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
-AUTO, NODE, EDGE, BALANCED, BINNED, EDGE_NOCHUNK = 0, 1, 2, 3, 4, 5
+AUTO, NODE, EDGE, BALANCED, BINNED, EDGE_NOCHUNK, HIER = 0, 1, 2, 3, 4, 5, 6
 STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED, "binned": BINNED,
-              "edge_nochunk": EDGE_NOCHUNK}
+              "edge_nochunk": EDGE_NOCHUNK, "hier": HIER}
 BFS_INF = 2**31 - 1
 SSSP_INF = 2**32 - 1
 

@@ -54,6 +54,8 @@ def test_workspace_formulas():
     cap = n + m // 64 + 1
     exp_binned = ctl + bfs_state + 2 * (3 * al(4 * cap) + al(4 * tiles))
     assert lbgmod.workspace_bytes(n, m, "binned", False) == exp_binned
+    # hierarchical: two sublists of n worklist indices
+    assert lbgmod.workspace_bytes(n, m, "hier", False) == exp_bfs + 2 * al(4 * n)
     # CSR strategies stay O(n + m / tile); the edge one grows with m
     assert lbgmod.workspace_bytes(n, 50 * m, "balanced", False) < lbgmod.workspace_bytes(n, 50 * m, "edge", False) / 10
     # invalid arguments
@@ -88,6 +90,7 @@ def _sssp(n=10, m=20, src=0, weights=FAKE, strategy=lbgmod.BALANCED, coo=None, w
     (dict(ws=None), lbgmod.EINVAL),
     (dict(cols=None), lbgmod.EINVAL),
     (dict(strategy=7), lbgmod.EINVAL),
+    (dict(strategy=-2), lbgmod.EINVAL),
     (dict(strategy=lbgmod.EDGE_NOCHUNK), lbgmod.EINVAL),  # no coo_src
     (dict(strategy=lbgmod.EDGE), lbgmod.EINVAL),          # no coo_src
     (dict(ws=ctypes.c_void_p(0x10010)), lbgmod.EINVAL),  # misaligned workspace

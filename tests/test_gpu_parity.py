@@ -16,8 +16,8 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 from paper_1711_00231_amd import lbg  # noqa: E402  (fails loudly if liblbg.so is missing)
 
-STRATS = ["node", "edge", "balanced", "binned", "edge_nochunk"]
-FULL_STRATS = ["node", "edge", "balanced", "binned"]  # the ablation is too slow at full size
+STRATS = ["node", "edge", "balanced", "binned", "hier", "edge_nochunk"]
+FULL_STRATS = ["node", "edge", "balanced", "binned", "hier"]  # the ablation is too slow at full size
 O = oracle.get()
 
 
