@@ -261,9 +261,8 @@ def run_plain(args, lbg, torch, dev):
 # ----------------------------------------------------------- strategies --
 def run_strategies(lbg, torch, g, srcs, dev):
     """Node-based vs edge-based vs hierarchical vs balanced vs degree-binned
-    assignment on the
-    same graph: BFS and SSSP from two sources each (binned with bins
-    autotuned on two other sources)."""
+    assignment on the same graph: BFS and SSSP from two sources each (binned
+    with bins autotuned on two other sources)."""
     dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev, with_coo=True)
     deg = g.degrees
     tuned = lbg.autotune_bins(dg, [int(x) for x in srcs[2:4]])
