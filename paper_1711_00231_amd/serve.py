@@ -10,6 +10,15 @@ resources return to the pools, and latency = completion - arrival is
 recorded.  Admission is first-come first-served: a request that does not fit
 blocks the ones behind it, so no request starves.
 
+Failure handling: a request whose footprint can never fit (more result rows
+than the engine holds, or an uploaded graph larger than a region) is
+rejected at admission instead of blocking the queue; a request with a
+timeout that is still waiting for admission that long after its arrival is
+dropped; Server.cancel(rid) withdraws a request from any thread.  A cancelled
+request that is still queued never runs; one that is already running
+finishes (a query costs milliseconds) and its result is discarded.  Every
+request ends with a status: done, rejected, timeout or cancelled.
+
 Admission is size-aware when a PlainLane is given: a query on a large
 resident instance already fills the GPU by itself, so batching it would only
 add per-level synchronisation; such queries are served first-come
@@ -75,7 +84,9 @@ class Request:
     instance: str | None    # a resident instance, or None for an uploaded graph
     src: int                # local source id within the instance
     graph: object = None    # uploaded graph (graphgen.Graph) when instance is None
+    timeout: float | None = None  # longest wait for admission (s); None: server default
     # filled by the server
+    status: str = ""        # done | rejected | timeout | cancelled
     admitted: float = -1.0
     done: float = -1.0
     slot: int = -1
@@ -99,7 +110,8 @@ class Instance:
 
 @dataclass
 class ServeReport:
-    completed: list = field(default_factory=list)
+    completed: list = field(default_factory=list)  # status "done"
+    dropped: list = field(default_factory=list)    # rejected, timed out or cancelled
     wall: float = 0.0
     steps: int = 0
 
@@ -107,6 +119,10 @@ class ServeReport:
         lat = np.array([r.latency for r in self.completed]) * 1e3
         arcs = sum(r.arcs for r in self.completed)
         out = {"requests": len(self.completed), "wall_s": round(self.wall, 4), "steps": self.steps}
+        for st in ("rejected", "timeout", "cancelled"):
+            k = sum(r.status == st for r in self.dropped)
+            if k:
+                out[st] = k
         if lat.size:
             out.update({"p50_ms": round(float(np.percentile(lat, 50)), 4),
                         "p99_ms": round(float(np.percentile(lat, 99)), 4),
@@ -142,6 +158,12 @@ class PlainLane:
                 r = self._q.get()
                 if r is None:
                     return
+                if r.status == "cancelled":  # withdrawn while queued here
+                    r.done = clock() - t0
+                    with self._lock:
+                        self._done.append(r)
+                        self._pending -= 1
+                    continue
                 try:
                     res = self.solve(r, keep_results)
                 except Exception as exc:  # surfaced by the serving loop
@@ -188,34 +210,59 @@ class Server:
     instances: name -> Instance (node range of a resident graph in the packed
     CSR).  upload: optional UploadArena for per-request graphs.  plain:
     optional PlainLane for queries on large resident instances.
+    timeout: default longest wait for admission, in seconds (None: no limit;
+    a request's own timeout takes precedence).
     """
 
+    ADMITTED, WAIT, REJECT = 0, 1, 2
+
     def __init__(self, engine, instances: dict, upload=None, levels_per_step: int = 1,
-                 keep_results: bool = False, plain: PlainLane | None = None):
+                 keep_results: bool = False, plain: PlainLane | None = None,
+                 timeout: float | None = None):
         self.engine = engine
         self.instances = instances
         self.upload = upload
         self.levels_per_step = int(levels_per_step)
         self.keep_results = keep_results
         self.plain = plain
+        self.timeout = timeout
         self.rows = RowAllocator(engine.max_rows)
         self.inflight: dict[int, Request] = {}
+        self._cancel_lock = threading.Lock()
+        self._cancels: set = set()
+
+    def cancel(self, rid: int) -> None:
+        """Withdraw request `rid`; safe to call from any thread while run()
+        is serving.  Takes effect at the next pass of the serving loop."""
+        with self._cancel_lock:
+            self._cancels.add(rid)
 
     # -- admission ---------------------------------------------------------
-    def _try_admit(self, r: Request, now: float) -> bool:
+    def _fits_ever(self, r: Request) -> bool:
+        if r.instance is not None:
+            inst = self.instances[r.instance]
+            if self.plain is not None and self.plain.wants(inst.arcs):
+                return True
+            return inst.hi - inst.lo <= self.engine.max_rows
+        if self.upload is None:
+            raise ValueError("request carries a graph but the server has no upload arena")
+        g = r.graph
+        return g.n < self.upload.node_cap and g.m <= self.upload.arc_cap and g.n <= self.engine.max_rows
+
+    def _try_admit(self, r: Request, now: float) -> int:
+        if not self._fits_ever(r):
+            return self.REJECT
         if r.instance is not None:
             inst = self.instances[r.instance]
             lo, hi, arcs = inst.lo, inst.hi, inst.arcs
             if self.plain is not None and self.plain.wants(arcs):
                 r.admitted, r.arcs, r.length = now, arcs, hi - lo
                 self.plain.submit(r)
-                return True
+                return self.ADMITTED
         else:
-            if self.upload is None:
-                raise ValueError("request carries a graph but the server has no upload arena")
             region = self.upload.acquire()
             if region is None:
-                return False
+                return self.WAIT
             lo, hi, arcs = self.upload.load(region, r.graph)
             r.region = region
         row = self.rows.alloc(hi - lo)
@@ -223,22 +270,34 @@ class Server:
             if r.region >= 0:
                 self.upload.release(r.region)
                 r.region = -1
-            return False
+            return self.WAIT
         slot = self.engine.submit(lo + r.src, lo, hi, r.kind, row)
         if slot < 0:
             self.rows.release(row, hi - lo)
             if r.region >= 0:
                 self.upload.release(r.region)
                 r.region = -1
-            return False
+            return self.WAIT
         r.slot, r.row, r.length, r.arcs, r.admitted = slot, row, hi - lo, arcs, now
         self.inflight[slot] = r
-        return True
+        return self.ADMITTED
+
+    def _expired(self, r: Request, now: float) -> bool:
+        t = r.timeout if r.timeout is not None else self.timeout
+        return t is not None and now - r.arrival > t
+
+    def _apply_cancels(self, by_rid: dict) -> None:
+        with self._cancel_lock:
+            ids, self._cancels = self._cancels, set()
+        for rid in ids:
+            r = by_rid.get(rid)
+            if r is not None and r.status == "":
+                r.status = "cancelled"
 
     def _complete(self, slot: int, now: float) -> Request:
         r = self.inflight.pop(slot)
         r.done = now
-        if self.keep_results:
+        if self.keep_results and r.status != "cancelled":
             r.result = self.engine.rows[r.row: r.row + r.length].cpu().numpy().copy()
         self.engine.release(slot)
         self.rows.release(r.row, r.length)
@@ -246,12 +305,19 @@ class Server:
             self.upload.release(r.region)
         return r
 
+    @staticmethod
+    def _file(report: ServeReport, r: Request) -> None:
+        if r.status == "":
+            r.status = "done"
+        (report.completed if r.status == "done" else report.dropped).append(r)
+
     # -- loop --------------------------------------------------------------
     def run(self, requests, clock=time.perf_counter, replay: bool = False) -> ServeReport:
         """Serve `requests` (sorted by arrival).  With replay=False arrivals
         follow the wall clock (idle periods are waited out); with replay=True
         the run starts each request as soon as possible in arrival order."""
         pending = list(requests)
+        by_rid = {r.rid: r for r in pending}
         report = ServeReport()
         t0 = clock()
         lane = self.plain
@@ -260,24 +326,38 @@ class Server:
         i = 0
         try:
             while i < len(pending) or self.inflight or (lane is not None and lane.busy()):
+                self._apply_cancels(by_rid)
                 now = clock() - t0
                 blocked = False  # an arrived request did not fit
-                while i < len(pending) and (replay or pending[i].arrival <= now):
-                    if not self._try_admit(pending[i], now):
-                        blocked = True
-                        break
+                while i < len(pending) and (replay or pending[i].arrival <= now
+                                            or pending[i].status == "cancelled"):
+                    r = pending[i]
+                    if r.status == "" and self._expired(r, now):
+                        r.status = "timeout"
+                    if r.status == "":
+                        got = self._try_admit(r, now)
+                        if got == self.WAIT:
+                            blocked = True
+                            break
+                        if got == self.REJECT:
+                            r.status = "rejected"
+                    if r.status != "":  # rejected, timed out or cancelled before admission
+                        r.done = now
+                        report.dropped.append(r)
                     i += 1
                 if lane is not None:
-                    report.completed.extend(lane.drain())
+                    for r in lane.drain():
+                        self._file(report, r)
                 if not self.inflight:
                     if i >= len(pending):
                         if lane is not None and lane.busy():
                             time.sleep(0.0001)
                         continue
                     if blocked and not (lane is not None and lane.busy()):
-                        # it arrived, nothing runs, and it still does not fit
+                        # it fits the pools' sizes, yet nothing runs and it still
+                        # does not fit: the engine has no slot or the arena no region
                         raise RuntimeError(f"request {pending[i].rid} can never be admitted "
-                                           "(larger than the server's capacity)")
+                                           "(the engine or the upload arena has no capacity)")
                     wait = pending[i].arrival - (clock() - t0)
                     time.sleep(min(max(wait, 0.0), 0.001) if wait > 0 else 0.0001)
                     continue
@@ -285,12 +365,13 @@ class Server:
                 report.steps += 1
                 now = clock() - t0
                 for slot in done:
-                    report.completed.append(self._complete(slot, now))
+                    self._file(report, self._complete(slot, now))
         finally:
             if lane is not None:
                 lane.stop()
         if lane is not None:
-            report.completed.extend(lane.drain())
+            for r in lane.drain():
+                self._file(report, r)
         report.wall = clock() - t0
         return report
 

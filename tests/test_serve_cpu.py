@@ -121,12 +121,92 @@ def test_capacity_blocks_but_never_starves():
     _check_results(rep, gs)
 
 
-def test_too_large_request_raises():
+def test_too_large_request_rejected_others_served():
     gs, u, inst = _setup()
-    eng = FakeEngine(u, max_queries=2, max_rows=100)
-    reqs = [serve.Request(0, 0.0, serve.KIND_BFS, "g0", 0)]
+    small = min(inst, key=lambda k: inst[k].hi - inst[k].lo)
+    big = max(inst, key=lambda k: inst[k].hi - inst[k].lo)
+    eng = FakeEngine(u, max_queries=2, max_rows=inst[small].hi - inst[small].lo)
+    reqs = [serve.Request(0, 0.0, serve.KIND_BFS, big, 0),
+            serve.Request(1, 0.0, serve.KIND_SSSP, small, 3)]
+    rep = serve.Server(eng, inst, keep_results=True).run(reqs, replay=True)
+    assert [r.rid for r in rep.dropped] == [0] and rep.dropped[0].status == "rejected"
+    assert [r.rid for r in rep.completed] == [1] and rep.completed[0].status == "done"
+    _check_results(rep, gs)
+    assert rep.summary()["rejected"] == 1
+
+
+def test_engine_without_slots_raises():
+    gs, u, inst = _setup()
+    eng = FakeEngine(u, max_queries=0, max_rows=10000)
     with pytest.raises(RuntimeError, match="never be admitted"):
-        serve.Server(eng, inst).run(reqs, replay=True)
+        serve.Server(eng, inst).run([serve.Request(0, 0.0, serve.KIND_BFS, "g0", 0)], replay=True)
+
+
+class _Clock:
+    """Deterministic clock: advances by `dt` at every reading."""
+
+    def __init__(self, dt):
+        self.t, self.dt = 0.0, dt
+
+    def __call__(self):
+        self.t += self.dt
+        return self.t
+
+
+def test_admission_timeout_drops_waiting_requests():
+    gs, u, inst = _setup()
+    # one slot; every query holds it for `lag` steps, so later requests wait
+    eng = FakeEngine(u, max_queries=1, max_rows=10000, lag=5)
+    reqs = [serve.Request(i, 0.0, serve.KIND_BFS, "g2", i) for i in range(6)]
+    reqs[5].timeout = 1e9  # its own timeout overrides the server's
+    srv = serve.Server(eng, inst, keep_results=True, timeout=0.05)
+    rep = srv.run(reqs, replay=True, clock=_Clock(0.004))
+    done = sorted(r.rid for r in rep.completed)
+    late = sorted(r.rid for r in rep.dropped)
+    assert 0 in done and 5 in done and late and set(done) | set(late) == set(range(6))
+    for r in rep.dropped:
+        assert r.status == "timeout" and r.done - r.arrival > 0.05 and r.admitted < 0
+    for r in rep.completed:
+        assert r.admitted - r.arrival <= 0.05 or r.rid == 5
+    _check_results(rep, gs)
+    assert not eng.slots and srv.rows.in_use == 0
+
+
+def test_cancel_queued_and_running():
+    gs, u, inst = _setup()
+
+    class CancellingEngine(FakeEngine):
+        def step(self, levels=1):
+            if self.tick == 0:
+                srv.cancel(0)   # running by now
+                srv.cancel(3)   # still queued
+                srv.cancel(99)  # unknown ids are ignored
+            return super().step(levels)
+
+    eng = CancellingEngine(u, max_queries=2, max_rows=10000, lag=3)
+    reqs = [serve.Request(i, 0.0, serve.KIND_SSSP, "g1", i) for i in range(5)]
+    srv = serve.Server(eng, inst, keep_results=True)
+    rep = srv.run(reqs, replay=True)
+    by = {r.rid: r for r in rep.completed + rep.dropped}
+    assert by[0].status == "cancelled" and by[0].admitted >= 0 and by[0].result is None
+    assert by[3].status == "cancelled" and by[3].admitted < 0
+    assert sorted(r.rid for r in rep.completed) == [1, 2, 4]
+    _check_results(rep, gs)
+    assert not eng.slots and srv.rows.in_use == 0
+    assert rep.summary()["cancelled"] == 2
+
+
+def test_upload_larger_than_region_rejected():
+    gs, u, inst = _setup()
+
+    class Arena:
+        node_cap, arc_cap = 100, 400
+
+    g = graphgen.uniform(n=500, k=4, salt=7)
+    eng = FakeEngine(u, max_queries=2, max_rows=10000)
+    srv = serve.Server(eng, inst, upload=Arena())
+    rep = srv.run([serve.Request(0, 0.0, serve.KIND_BFS, None, 0, graph=g)], replay=True)
+    assert rep.dropped[0].status == "rejected" and not rep.completed
 
 
 def test_wall_clock_arrivals():
@@ -207,3 +287,38 @@ def test_plain_lane_error_surfaces():
     reqs = serve.poisson_requests(1e4, 5, inst, seed=3)
     with pytest.raises(ValueError, match="solver failed"):
         serve.Server(eng, inst, plain=lane).run(reqs, replay=True)
+
+
+def test_plain_lane_skips_cancelled_requests():
+    """A request cancelled while it waits in the plain lane's queue is never
+    solved; the lane's queue keeps its order for the rest."""
+    import threading
+
+    gs, u, inst = _setup()
+    gate = threading.Event()
+    solved = []
+
+    def solve(r, keep):
+        if r.rid == 0:
+            gate.wait(10)  # hold the lane until the cancels are in
+        solved.append(r.rid)
+        g = gs[int(r.instance[1:])]
+        return O.bfs(g.offsets, g.cols, r.src)
+
+    lane = serve.PlainLane(solve, big_arcs=0)
+    eng = FakeEngine(u, max_queries=2, max_rows=6000)
+    reqs = [serve.Request(i, 0.0, serve.KIND_BFS, "g0", i) for i in range(4)]
+    srv = serve.Server(eng, inst, keep_results=True, plain=lane)
+
+    def cancel_then_release():
+        srv.cancel(2)
+        import time
+        time.sleep(0.05)  # the loop applies the cancel on its next pass
+        gate.set()
+
+    threading.Thread(target=cancel_then_release).start()
+    rep = srv.run(reqs, replay=True)
+    assert solved == [0, 1, 3]
+    assert sorted(r.rid for r in rep.completed) == [0, 1, 3]
+    assert [(r.rid, r.status) for r in rep.dropped] == [(2, "cancelled")]
+    _check_results(rep, gs)
