@@ -198,6 +198,29 @@ def test_autotune_bins_keeps_results():
         lbg.set_bins(**saved)
 
 
+def test_tuned_bins_cache_round_trip(tmp_path):
+    """A cache miss tunes on the device and stores the result; a later hit
+    sets the same parameters without tuning; results stay the oracle's."""
+    from paper_1711_00231_amd import tuning
+
+    saved = lbg.get_bins()
+    try:
+        g = graphgen.rmat(13)
+        dg = _dev(g)
+        srcs = graphgen.sources(g, 2, graphgen.FAMILY_RMAT)
+        cache = tuning.BinsCache(str(tmp_path / "bins.json"))
+        best, hit = tuning.tuned_bins(dg, srcs, "rmat", cache)
+        assert not hit and lbg.get_bins() == best
+        assert cache.get(tuning.cache_key("rmat", g.n, g.m, tuning.device_arch(dg.offsets.device))) == best
+        lbg.set_bins(0, 0, 0)
+        again, hit = tuning.tuned_bins(dg, srcs, "rmat", cache,
+                                       tune=lambda *a: pytest.fail("tuned on a cache hit"))
+        assert hit and again == best and lbg.get_bins() == best
+        _check(g, dg, srcs, "binned")
+    finally:
+        lbg.set_bins(**saved)
+
+
 def test_repeat_runs_identical():
     """Relaxation order differs from run to run; results must not."""
     g = graphgen.rmat(14)
