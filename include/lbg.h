@@ -34,6 +34,17 @@
  *   LBG_EDGE_NOCHUNK  LBG_EDGE without work chunking: every arc of an
  *                 improved node is reserved with its own atomic on the tail
  *                 (the ablation of Section IV-D; slow by design)
+ *   LBG_SLICED    workload decomposition per destination slice: node ids are
+ *                 cut into 8 slices (one per XCD of the MI355X), every
+ *                 adjacency list is grouped by destination slice once
+ *                 (lbg_slice_graph); a frontier node with at least
+ *                 lbg_set_slice_min() arcs is split into its per-slice
+ *                 segments (the node splitting of Section III-B, pieces by
+ *                 destination), each slice's segments are tiled as in
+ *                 LBG_BALANCED and expanded by the workgroups of one XCD, so
+ *                 their random node-state accesses stay within that XCD's L2;
+ *                 smaller nodes are tiled together by all workgroups
+ *                 (lbg_bfs_sliced, lbg_sssp_sliced)
  *   LBG_AUTO      currently LBG_BALANCED
  *
  * Conventions for every entry point
@@ -85,13 +96,15 @@ typedef enum {
   LBG_BALANCED = 3,
   LBG_BINNED = 4,
   LBG_EDGE_NOCHUNK = 5,
-  LBG_HIER = 6
+  LBG_HIER = 6,
+  LBG_SLICED = 7
 } lbg_strategy;
 
 /* Counters of one solve (host struct, filled when `stats` is not NULL).
  * levels: number of non-empty frontiers (BFS: eccentricity of src + 1;
  *         SSSP: Bellman-Ford iterations).
- * frontier_entries: total worklist entries processed (nodes; LBG_EDGE: edges).
+ * frontier_entries: total worklist entries processed (nodes; LBG_EDGE: edges;
+ *         LBG_SLICED: (node, slice) pairs).
  * edges_scanned: total arcs relaxed (BFS: the arcs leaving reached nodes;
  *         SSSP: at least that, re-relaxations included).
  * updates: successful distance improvements (SSSP) or discoveries (BFS).
@@ -131,6 +144,53 @@ int lbg_bfs(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, i
 int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
              int64_t m, int32_t src, uint32_t* dist_out, void* workspace, size_t workspace_bytes,
              int32_t strategy, const int32_t* coo_src, lbg_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Destination-sliced graphs (LBG_SLICED; the workload decomposition of
+ * Section III-A, cut per destination slice).
+ *
+ * Slices: node v belongs to slice v / S, S = lbg_slice_nodes(n) =
+ * ceil(n / 8) rounded up to a multiple of 64; there are at most 8 slices.
+ *
+ * lbg_slice_graph: from a CSR graph (offsets[n+1], cols[m], optional
+ * weights[m]; conventions above) writes
+ *   slice_offsets[8n + 1] int32: the arcs of node u into slice x are
+ *     positions slice_offsets[8u + x] .. slice_offsets[8u + x + 1] - 1 of
+ *     cols_out (so slice_offsets[8u] = offsets[u], slice_offsets[8n] = m);
+ *   cols_out[m], weights_out[m]: each adjacency list regrouped by destination
+ *     slice, arcs of one slice in their input order.
+ * (offsets, cols_out, weights_out) is a CSR of the same graph, valid for
+ * every other strategy.  weights and weights_out are both NULL (BFS only) or
+ * both given (when m > 0).  All outputs are device buffers the caller allocates; they
+ * must not overlap the inputs.  Offsets outside [0, m] are clamped (run
+ * lbg_validate_csr first on untrusted input).  Returns when the outputs are
+ * written; LBG_EINVAL / LBG_ERANGE on bad arguments.
+ *
+ * lbg_bfs_sliced / lbg_sssp_sliced: as lbg_bfs / lbg_sssp with strategy
+ * LBG_SLICED, on the output of lbg_slice_graph: offsets = the CSR offsets
+ * (unchanged by the grouping), slice_offsets, cols = cols_out, weights =
+ * weights_out; workspace of at least
+ * lbg_workspace_bytes(n, m, LBG_SLICED, is_sssp) bytes (for each of the 8
+ * slice lists and the mixed list: two worklists of min(n, m) entries and
+ * their tile marks).  Results are identical to every other strategy's.
+ * lbg_bfs / lbg_sssp reject LBG_SLICED with LBG_EINVAL.
+ *
+ * lbg_set_slice_min: process-wide degree from which a frontier node is split
+ * by destination slice (default 512; 0 = every node, INT32_MAX = none, which
+ * leaves one list tiled by every workgroup).  LBG_EINVAL if negative; affects
+ * sliced solves that start later.  lbg_get_slice_min returns it. */
+int32_t lbg_slice_nodes(int32_t n);
+int lbg_set_slice_min(int32_t min_degree);
+int32_t lbg_get_slice_min(void);
+int lbg_slice_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, int32_t* slice_offsets, int32_t* cols_out, uint32_t* weights_out,
+                    void* stream);
+int lbg_bfs_sliced(const int32_t* offsets, const int32_t* slice_offsets, const int32_t* cols, int32_t n,
+                   int64_t m, int32_t src, int32_t* levels_out, void* workspace, size_t workspace_bytes,
+                   lbg_stats* stats, void* stream);
+int lbg_sssp_sliced(const int32_t* offsets, const int32_t* slice_offsets, const int32_t* cols,
+                    const uint32_t* weights, int32_t n, int64_t m, int32_t src, uint32_t* dist_out,
+                    void* workspace, size_t workspace_bytes, lbg_stats* stats, void* stream);
 
 /* Structural check of a CSR graph on the device: offsets[0] == 0,
  * non-decreasing offsets, offsets[n] == m, every col in [0, n).  Needs

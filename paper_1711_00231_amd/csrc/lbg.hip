@@ -12,6 +12,7 @@
 
 #include "../../include/lbg.h"
 #include "lbg_kernels.hpp"
+#include "lbg_sliced.hpp"
 
 namespace {
 
@@ -39,7 +40,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_HIER; }
+bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_SLICED; }
 bool edge_wl(int32_t s) { return s == LBG_EDGE || s == LBG_EDGE_NOCHUNK; }
 int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
@@ -72,6 +73,19 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
   if (edge_wl(s)) {
     L.edge_cap = static_cast<uint32_t>(m);
     for (int b = 0; b < 2; ++b) L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(m > 0 ? m : 1));
+  } else if (s == LBG_SLICED) {
+    // per list (8 slices + the mixed one): a node has at most one entry per
+    // level (and only if it has arcs there), and the list's edge space is at
+    // most m
+    L.node_cap = static_cast<uint32_t>(std::max<int64_t>(1, std::min<int64_t>(n, m)));
+    L.tile_cap = static_cast<uint32_t>((m + lbg::kMinTile - 1) / lbg::kMinTile + 2);
+    const size_t ns = static_cast<size_t>(lbg::kLists) * L.node_cap;
+    for (int b = 0; b < 2; ++b) {
+      L.node[b] = take(sizeof(int32_t) * ns);
+      L.eprefix[b] = take(sizeof(uint32_t) * ns);
+      L.estart[b] = take(sizeof(int32_t) * ns);
+      L.tile[b] = take(sizeof(int32_t) * static_cast<size_t>(lbg::kLists) * L.tile_cap);
+    }
   } else {
     // split hubs add at most m / kMinMdt entries per level
     L.node_cap = static_cast<uint32_t>(n + (s == LBG_BINNED ? m / lbg::kMinMdt + 1 : 0));
@@ -120,6 +134,7 @@ int resident_grid(K kernel) {
 
 struct Grids {
   int bal[2][2], node[2], edge[2], edge_nc[2], multi[2], binned[2], hier[2];  // bal[is_sssp][narrow], multi[narrow]
+  int sliced[2][2];                                      // [is_sssp][narrow], a multiple of 8 (>= 8)
   bool small[2][2];                                      // small-frontier kernel fits the device
 };
 
@@ -135,6 +150,10 @@ bool fits_lds(K kernel) {
     return false;
   return fa.sharedSizeBytes <= static_cast<size_t>(max_lds) && fa.maxThreadsPerBlock >= lbg::kSmallBlock;
 }
+
+// Sliced expansion: every slice needs at least one workgroup; equal counts
+// per slice keep the XCDs evenly loaded.
+int slice_grid(int g) { return std::max(lbg::kXcds, g - g % lbg::kXcds); }
 
 const Grids& grids() {
   static std::mutex mu;
@@ -160,6 +179,10 @@ const Grids& grids() {
     g[dev].binned[1] = resident_grid(lbg::k_expand_binned<true>);
     g[dev].multi[0] = resident_grid(lbg::k_expand_balanced<true, false, true>);
     g[dev].multi[1] = resident_grid(lbg::k_expand_balanced<true, true, true>);
+    g[dev].sliced[0][0] = slice_grid(resident_grid(lbg::k_expand_sliced<false, false>));
+    g[dev].sliced[0][1] = slice_grid(resident_grid(lbg::k_expand_sliced<false, true>));
+    g[dev].sliced[1][0] = slice_grid(resident_grid(lbg::k_expand_sliced<true, false>));
+    g[dev].sliced[1][1] = slice_grid(resident_grid(lbg::k_expand_sliced<true, true>));
     g[dev].small[0][0] = fits_lds(lbg::k_expand_small<false, false>);
     g[dev].small[0][1] = fits_lds(lbg::k_expand_small<false, true>);
     g[dev].small[1][0] = fits_lds(lbg::k_expand_small<true, false>);
@@ -174,6 +197,7 @@ int grid_blocks() { return grids().bal[0][1]; }
 // Degree-bin parameters of LBG_BINNED solves (process-wide; lbg_set_bins).
 std::mutex g_bins_mu;
 lbg_bins g_bins{256, 16, 1024};  // what the autotuner picks on R-MAT scale 22
+int32_t g_slice_min = 512;       // LBG_SLICED: degree from which a node is split by slice
 
 // Host side of the profiling counters (see lbg_profile_enable).
 std::mutex g_prof_mu;
@@ -248,6 +272,8 @@ struct Problem {
   int is_sssp;
   lbg_stats* stats;
   hipStream_t stream;
+  bool sliced = false;           // called through lbg_bfs_sliced / lbg_sssp_sliced
+  const int32_t* soff = nullptr;  // their slice offsets
 };
 
 int check_common(const Problem& P) {
@@ -261,6 +287,9 @@ int check_common(const Problem& P) {
   if (P.is_sssp && P.m > 0 && !P.weights) return fail(LBG_EINVAL, "null weights pointer with m > 0");
   if (edge_wl(resolve(P.strategy)) && !P.coo_src)
     return fail(LBG_EINVAL, "LBG_EDGE needs the coo_src array");
+  if ((resolve(P.strategy) == LBG_SLICED) != P.sliced)
+    return fail(LBG_EINVAL, "LBG_SLICED runs through lbg_bfs_sliced / lbg_sssp_sliced only");
+  if (P.sliced && !P.soff) return fail(LBG_EINVAL, "null slice_offsets pointer");
   if (reinterpret_cast<uintptr_t>(P.ws) % kAlign)
     return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
   const size_t need = layout(P.n, P.m, P.strategy, P.is_sssp).total;
@@ -308,6 +337,16 @@ int solve(const Problem& P) {
   a.node_cap = Lay.node_cap;
   a.tile_cap = Lay.tile_cap;
   a.edge_cap = Lay.edge_cap;
+  const bool sl = strat == LBG_SLICED;
+  if (sl) {
+    a.soff = P.soff;
+    a.sliced = 1u;
+    a.scap = Lay.node_cap;
+    a.stcap = Lay.tile_cap;
+    a.slice_nodes = lbg::slice_size(a.n);
+    std::lock_guard<std::mutex> lk(g_bins_mu);
+    a.slice_min = static_cast<uint32_t>(g_slice_min);
+  }
   if (strat == LBG_BINNED) {
     std::lock_guard<std::mutex> lk(g_bins_mu);
     a.mdt = static_cast<uint32_t>(g_bins.mdt);
@@ -328,7 +367,8 @@ int solve(const Problem& P) {
   const Grids& GR = grids();
   const int sv = P.is_sssp ? 1 : 0;
   // 32-bit element offsets are enough when every array stays below 4 GiB
-  const bool narrow = P.n < (1 << 29) && P.m < (int64_t{1} << 30);
+  // (the slice offsets have 8n + 1 entries)
+  const bool narrow = P.n < (sl ? (1 << 26) : (1 << 29)) && P.m < (int64_t{1} << 30);
   const int nw = narrow ? 1 : 0;
   const int init_blocks = static_cast<int>(
       std::min<int64_t>(std::max<int64_t>((static_cast<int64_t>(P.n) + lbg::kBlock - 1) / lbg::kBlock, 1), 4096));
@@ -348,7 +388,10 @@ int solve(const Problem& P) {
     hier_subs = std::max<uint32_t>(1, (mx + hier_mdt - 1) / hier_mdt);
   }
 
-  if (P.is_sssp) {
+  if (sl) {
+    if (P.is_sssp) hipLaunchKernelGGL((lbg::k_init_sliced<true>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
+    else hipLaunchKernelGGL((lbg::k_init_sliced<false>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
+  } else if (P.is_sssp) {
     if (edge_wl(strat)) hipLaunchKernelGGL((lbg::k_init<true, true>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
     else hipLaunchKernelGGL((lbg::k_init<true, false>), dim3(init_blocks), dim3(lbg::kBlock), 0, st, a, P.src);
   } else {
@@ -364,6 +407,10 @@ int solve(const Problem& P) {
         case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<true, true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_EDGE_NOCHUNK: hipLaunchKernelGGL((lbg::k_expand_edge<true, false>), dim3(GR.edge_nc[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<true>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_SLICED:
+          if (narrow) hipLaunchKernelGGL((lbg::k_expand_sliced<true, true>), dim3(GR.sliced[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          else hipLaunchKernelGGL((lbg::k_expand_sliced<true, false>), dim3(GR.sliced[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          break;
         case LBG_HIER:
           hipLaunchKernelGGL(lbg::k_hier_reset, dim3(1), dim3(64), 0, st, a.ctl);
           for (uint32_t k = 0; k < hier_subs; ++k)
@@ -380,6 +427,10 @@ int solve(const Problem& P) {
         case LBG_EDGE: hipLaunchKernelGGL((lbg::k_expand_edge<false, true>), dim3(GR.edge[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_EDGE_NOCHUNK: hipLaunchKernelGGL((lbg::k_expand_edge<false, false>), dim3(GR.edge_nc[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
         case LBG_BINNED: hipLaunchKernelGGL((lbg::k_expand_binned<false>), dim3(GR.binned[sv]), dim3(lbg::kBlock), 0, st, a, L); break;
+        case LBG_SLICED:
+          if (narrow) hipLaunchKernelGGL((lbg::k_expand_sliced<false, true>), dim3(GR.sliced[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          else hipLaunchKernelGGL((lbg::k_expand_sliced<false, false>), dim3(GR.sliced[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          break;
         case LBG_HIER:
           hipLaunchKernelGGL(lbg::k_hier_reset, dim3(1), dim3(64), 0, st, a.ctl);
           for (uint32_t k = 0; k < hier_subs; ++k)
@@ -450,12 +501,18 @@ int solve(const Problem& P) {
     if (host->error)
       return fail(LBG_EOVERFLOW, "device capacity guard tripped (flags 0x%x)", host->error);
     L = host->levels;
-    const uint32_t ef = static_cast<uint32_t>(host->ctr[L % 3]);
+    uint64_t ef = static_cast<uint32_t>(host->ctr[L % 3]), nfr = host->ctr[L % 3] >> 32;
+    if (sl) {  // the mixed list's tail (ctr) plus the 8 slice tails
+      for (int x = 0; x < lbg::kXcds; ++x) {
+        ef += static_cast<uint32_t>(host->xstat[x][4 + L % 3]);
+        nfr += host->xstat[x][4 + L % 3] >> 32;
+      }
+    }
     if (ef == 0u) break;
     if (L > level_cap)
       return fail(LBG_EINTERNAL, "more than n + 1 levels; the CSR is probably malformed");
     const bool was_small = small;
-    small = small_ok && ef <= lbg::kSmallE && (host->ctr[L % 3] >> 32) <= lbg::kSmallF &&
+    small = small_ok && ef <= lbg::kSmallE && nfr <= lbg::kSmallF &&
             !(was_small && L == L_prev);  // a small step always advances; never spin
     if (was_small && !small) batch = 8;
     L_prev = L;
@@ -1087,6 +1144,58 @@ int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weight
              int32_t strategy, const int32_t* coo_src, lbg_stats* stats, void* stream) {
   Problem P{offsets, cols, weights, coo_src, n, m, src, dist_out, workspace, workspace_bytes,
             strategy, 1, stats, static_cast<hipStream_t>(stream)};
+  return solve(P);
+}
+
+int lbg_slice_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, int32_t* slice_offsets, int32_t* cols_out, uint32_t* weights_out,
+                    void* stream) {
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX)
+    return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
+  if (!offsets || !slice_offsets || (m > 0 && (!cols || !cols_out)))
+    return fail(LBG_EINVAL, "null offsets/slice_offsets/cols/cols_out pointer");
+  if (m > 0 && (weights == nullptr) != (weights_out == nullptr))
+    return fail(LBG_EINVAL, "weights and weights_out must both be given or both be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int blocks = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(n) + lbg::kWaves - 1) / lbg::kWaves, 16384));
+  hipLaunchKernelGGL(lbg::k_slice_group, dim3(blocks), dim3(lbg::kBlock), 0, st, offsets, cols, weights,
+                     static_cast<uint32_t>(n), static_cast<uint32_t>(m), lbg::slice_size(static_cast<uint32_t>(n)),
+                     slice_offsets, cols_out, weights_out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return LBG_OK;
+}
+
+int lbg_set_slice_min(int32_t min_degree) {
+  if (min_degree < 0) return fail(LBG_EINVAL, "slice_min must be >= 0 (got %d)", min_degree);
+  std::lock_guard<std::mutex> lk(g_bins_mu);
+  g_slice_min = min_degree;
+  return LBG_OK;
+}
+
+int32_t lbg_get_slice_min(void) {
+  std::lock_guard<std::mutex> lk(g_bins_mu);
+  return g_slice_min;
+}
+
+int32_t lbg_slice_nodes(int32_t n) {
+  return n > 0 ? static_cast<int32_t>(lbg::slice_size(static_cast<uint32_t>(n))) : 0;
+}
+
+int lbg_bfs_sliced(const int32_t* offsets, const int32_t* slice_offsets, const int32_t* cols, int32_t n,
+                   int64_t m, int32_t src, int32_t* levels_out, void* workspace, size_t workspace_bytes,
+                   lbg_stats* stats, void* stream) {
+  Problem P{offsets, cols, nullptr, nullptr, n, m, src, levels_out, workspace, workspace_bytes,
+            LBG_SLICED, 0, stats, static_cast<hipStream_t>(stream), true, slice_offsets};
+  return solve(P);
+}
+
+int lbg_sssp_sliced(const int32_t* offsets, const int32_t* slice_offsets, const int32_t* cols,
+                    const uint32_t* weights, int32_t n, int64_t m, int32_t src, uint32_t* dist_out,
+                    void* workspace, size_t workspace_bytes, lbg_stats* stats, void* stream) {
+  Problem P{offsets, cols, weights, nullptr, n, m, src, dist_out, workspace, workspace_bytes,
+            LBG_SLICED, 1, stats, static_cast<hipStream_t>(stream), true, slice_offsets};
   return solve(P);
 }
 

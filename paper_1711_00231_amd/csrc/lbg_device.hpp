@@ -62,7 +62,9 @@ struct Ctl {
   unsigned int pad3;
   unsigned long long pad1[4];
   // [x][0] updates, [x][1] global atomics issued; [x][2], [x][3] the same for
-  // levels run by the small-frontier kernel
+  // levels run by the small-frontier kernel; [x][4 + L % 3] the packed tail
+  // (nodes << 32 | edges) of slice x's worklist of level L (destination-
+  // sliced strategy)
   unsigned long long xstat[kXcds][16];
 };
 static_assert(sizeof(Ctl) == 128 + kXcds * 128, "Ctl layout");
@@ -114,6 +116,16 @@ struct KArgs {
   // is expanded by a workgroup, longer than t_wave by a wavefront, else by
   // one lane.
   uint32_t mdt, t_wave, t_block;
+  // Destination-sliced strategy: the arcs of node u into slice x (nodes
+  // [x * slice_nodes, (x + 1) * slice_nodes)) are soff[8u + x] ..
+  // soff[8u + x + 1] - 1; nodes with at least slice_min arcs are queued per
+  // slice, the others in one mixed list (list 8).  Worklist entries and tile
+  // marks of list x sit at x * scap / x * stcap of each frontier array.
+  const int32_t* soff;
+  uint32_t sliced;
+  uint32_t scap, stcap;
+  uint32_t slice_nodes;
+  uint32_t slice_min;
 };
 
 // Pieces of a node with d out-arcs under split size mdt, and piece k's

@@ -158,10 +158,8 @@ __device__ __forceinline__ bool relax(const KArgs& a, uint32_t L, int32_t v, uin
 // ------------------------------------------------------------------ init --
 // Output = infinity, source = 0, visited/stamp cleared, worklist 0 = {src}
 // (node strategies) or src's arcs (edge strategy).
-template <bool kSssp, bool kEdgeWl>
-__global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
-  const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t stride = gridDim.x * kBlock;
+template <bool kSssp>
+__device__ __forceinline__ void init_state(const KArgs& a, int32_t src, uint32_t gid, uint32_t stride) {
   for (uint32_t v = gid; v < a.n; v += stride) {
     if (kSssp) {
       a.dstate[v] = (v == static_cast<uint32_t>(src)) ? 0ull
@@ -185,6 +183,21 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
     const uint32_t fwords = a.words * kXcds;
     for (uint32_t w = gid; w < fwords; w += stride) a.xfilter[w] = 0u;
   }
+  if (gid == 0) {
+    a.ctl->error = 0u;
+    a.ctl->levels = 0u;
+    a.ctl->frontier_entries = 0ull;
+    a.ctl->edges_scanned = 0ull;
+    a.ctl->p_frontier_entries = 0ull;
+    a.ctl->p_edges_scanned = 0ull;
+  }
+}
+
+template <bool kSssp, bool kEdgeWl>
+__global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
+  const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t stride = gridDim.x * kBlock;
+  init_state<kSssp>(a, src, gid, stride);
   const int32_t s0 = a.offsets[src];
   const int32_t d0 = a.offsets[src + 1] - s0;
   if (kEdgeWl) {
@@ -208,12 +221,6 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
     a.ctl->ctr[0] = d0 > 0 ? ((nodes << 32) | static_cast<uint32_t>(d0)) : 0ull;
     a.ctl->ctr[1] = 0ull;
     a.ctl->ctr[2] = 0ull;
-    a.ctl->error = 0u;
-    a.ctl->levels = 0u;
-    a.ctl->frontier_entries = 0ull;
-    a.ctl->edges_scanned = 0ull;
-    a.ctl->p_frontier_entries = 0ull;
-    a.ctl->p_edges_scanned = 0ull;
   }
   if (gid < kXcds * 16) a.ctl->xstat[gid / 16][gid % 16] = 0ull;
 }
@@ -227,6 +234,12 @@ __global__ __launch_bounds__(kBlock) void k_sssp_finish(KArgs a) {
   const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
   if (static_cast<uint32_t>(c) != 0u) return;
+  if (a.sliced) {  // and the 8 slice lists
+    for (int x = 0; x < kXcds; ++x)
+      if (static_cast<uint32_t>(__hip_atomic_load(&a.ctl->xstat[x][4 + L % 3], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)) != 0u)
+        return;
+  }
   const uint32_t stride = gridDim.x * kBlock;
   for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += stride)
     a.dist[v] = static_cast<uint32_t>(a.dstate[v] >> 32);

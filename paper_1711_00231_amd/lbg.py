@@ -16,9 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbg.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
-AUTO, NODE, EDGE, BALANCED, BINNED, EDGE_NOCHUNK, HIER = 0, 1, 2, 3, 4, 5, 6
+AUTO, NODE, EDGE, BALANCED, BINNED, EDGE_NOCHUNK, HIER, SLICED = 0, 1, 2, 3, 4, 5, 6, 7
 STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED, "binned": BINNED,
-              "edge_nochunk": EDGE_NOCHUNK, "hier": HIER}
+              "edge_nochunk": EDGE_NOCHUNK, "hier": HIER, "sliced": SLICED}
 BFS_INF = 2**31 - 1
 SSSP_INF = 2**32 - 1
 
@@ -77,6 +77,18 @@ def _load():
     lib.lbg_sssp.restype = ctypes.c_int
     lib.lbg_sssp.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, sz, i32, vp,
                              ctypes.POINTER(Stats), vp]
+    lib.lbg_slice_nodes.restype = i32
+    lib.lbg_slice_nodes.argtypes = [i32]
+    lib.lbg_set_slice_min.restype = ctypes.c_int
+    lib.lbg_set_slice_min.argtypes = [i32]
+    lib.lbg_get_slice_min.restype = i32
+    lib.lbg_get_slice_min.argtypes = []
+    lib.lbg_slice_graph.restype = ctypes.c_int
+    lib.lbg_slice_graph.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp, vp]
+    lib.lbg_bfs_sliced.restype = ctypes.c_int
+    lib.lbg_bfs_sliced.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
+    lib.lbg_sssp_sliced.restype = ctypes.c_int
+    lib.lbg_sssp_sliced.argtypes = [vp, vp, vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
     lib.lbg_validate_csr.restype = ctypes.c_int
     lib.lbg_validate_csr.argtypes = [vp, vp, i32, i64, vp, sz, vp]
     lib.lbg_last_error.restype = ctypes.c_char_p
@@ -157,14 +169,15 @@ def workspace_bytes(n: int, m: int, strategy="balanced", sssp: bool = False) -> 
 @dataclass
 class DeviceGraph:
     """A CSR graph resident in device memory (int32 offsets/cols, uint32
-    weights stored in an int32 tensor).  ``coo_src`` is built only on demand
-    (the edge-based strategy needs it)."""
+    weights stored in an int32 tensor).  ``coo_src`` (edge-based strategy)
+    and ``sliced`` (destination-sliced strategy) are built only on demand."""
 
     offsets: torch.Tensor
     cols: torch.Tensor
     weights: torch.Tensor | None
     coo_src: torch.Tensor | None = None
     host_offsets: object = None  # numpy copy, used to size batched solves
+    sliced: "SlicedGraph | None" = None
 
     @property
     def n(self) -> int:
@@ -175,7 +188,7 @@ class DeviceGraph:
         return int(self.cols.numel())
 
     @classmethod
-    def from_numpy(cls, offsets, cols, weights=None, device="cuda", with_coo=False):
+    def from_numpy(cls, offsets, cols, weights=None, device="cuda", with_coo=False, with_slices=False):
         import numpy as np
 
         off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int32)).to(device)
@@ -186,7 +199,14 @@ class DeviceGraph:
         g = cls(off, c, w, None, np.ascontiguousarray(offsets, dtype=np.int64))
         if with_coo:
             g.ensure_coo()
+        if with_slices:
+            g.ensure_sliced()
         return g
+
+    def ensure_sliced(self, stream=None) -> "SlicedGraph":
+        if self.sliced is None:
+            self.sliced = slice_graph(self, stream=stream)
+        return self.sliced
 
     def ensure_coo(self) -> torch.Tensor:
         if self.coo_src is None:
@@ -196,6 +216,42 @@ class DeviceGraph:
             if self.coo_src.numel() == 0:
                 self.coo_src = torch.zeros(1, dtype=torch.int32, device=self.offsets.device)
         return self.coo_src
+
+
+@dataclass
+class SlicedGraph:
+    """The same graph with every adjacency list grouped by destination slice
+    (lbg_slice_graph): slice_offsets[8n + 1], cols, weights."""
+
+    slice_offsets: torch.Tensor
+    cols: torch.Tensor
+    weights: torch.Tensor | None
+    n: int
+    m: int
+
+
+def slice_nodes(n: int) -> int:
+    return int(lib.lbg_slice_nodes(int(n)))
+
+
+def set_slice_min(min_degree: int) -> None:
+    """Degree from which the sliced strategy splits a node by destination
+    slice (see lbg_set_slice_min)."""
+    _check(lib.lbg_set_slice_min(int(min_degree)))
+
+
+def get_slice_min() -> int:
+    return int(lib.lbg_get_slice_min())
+
+
+def slice_graph(g: DeviceGraph, stream=None) -> SlicedGraph:
+    dev = g.offsets.device
+    so = torch.empty(8 * g.n + 1, dtype=torch.int32, device=dev)
+    cols = torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+    w = None if g.weights is None else torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+    _check(lib.lbg_slice_graph(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, _ptr(so),
+                               _ptr(cols), _ptr(w), _stream(stream)))
+    return SlicedGraph(so, cols, w, g.n, g.m)
 
 
 class Workspace:
@@ -232,8 +288,14 @@ def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None 
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
-    rc = lib.lbg_bfs(_ptr(g.offsets), _ptr(g.cols), g.n, g.m, int(src), _ptr(out), _ptr(ws),
-                     ws.numel(), s, _ptr(coo), ctypes.byref(st) if stats else None, _stream(stream))
+    if s == SLICED:
+        sg = g.ensure_sliced(stream)
+        rc = lib.lbg_bfs_sliced(_ptr(g.offsets), _ptr(sg.slice_offsets), _ptr(sg.cols), g.n, g.m, int(src),
+                                _ptr(out), _ptr(ws), ws.numel(), ctypes.byref(st) if stats else None,
+                                _stream(stream))
+    else:
+        rc = lib.lbg_bfs(_ptr(g.offsets), _ptr(g.cols), g.n, g.m, int(src), _ptr(out), _ptr(ws),
+                         ws.numel(), s, _ptr(coo), ctypes.byref(st) if stats else None, _stream(stream))
     _check(rc)
     return (out, st.as_dict()) if stats else out
 
@@ -251,9 +313,17 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
-    rc = lib.lbg_sssp(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(src),
-                      _ptr(out), _ptr(ws), ws.numel(), s, _ptr(coo),
-                      ctypes.byref(st) if stats else None, _stream(stream))
+    if s == SLICED:
+        sg = g.ensure_sliced(stream)
+        if sg.weights is None:
+            raise ValueError("the sliced graph was built without weights")
+        rc = lib.lbg_sssp_sliced(_ptr(g.offsets), _ptr(sg.slice_offsets), _ptr(sg.cols), _ptr(sg.weights),
+                                 g.n, g.m, int(src), _ptr(out), _ptr(ws), ws.numel(),
+                                 ctypes.byref(st) if stats else None, _stream(stream))
+    else:
+        rc = lib.lbg_sssp(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(src),
+                          _ptr(out), _ptr(ws), ws.numel(), s, _ptr(coo),
+                          ctypes.byref(st) if stats else None, _stream(stream))
     _check(rc)
     return (out, st.as_dict()) if stats else out
 

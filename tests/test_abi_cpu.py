@@ -56,6 +56,13 @@ def test_workspace_formulas():
     assert lbgmod.workspace_bytes(n, m, "binned", False) == exp_binned
     # hierarchical: two sublists of n worklist indices
     assert lbgmod.workspace_bytes(n, m, "hier", False) == exp_bfs + 2 * al(4 * n)
+    # destination-sliced: per buffer, 8 slice lists + the mixed list, each of
+    # min(n, m) entries and its tile marks
+    cap = min(n, m)
+    exp_sliced = lambda state: ctl + state + 2 * (3 * al(4 * 9 * cap) + al(4 * 9 * tiles))
+    assert lbgmod.workspace_bytes(n, m, "sliced", False) == exp_sliced(bfs_state)
+    assert lbgmod.workspace_bytes(n, m, "sliced", True) == exp_sliced(sssp_state)
+    assert lbgmod.workspace_bytes(n, 0, "sliced", True) == ctl + sssp_state + 2 * (3 * al(4 * 9) + al(4 * 9 * 2))
     # CSR strategies stay O(n + m / tile); the edge one grows with m
     assert lbgmod.workspace_bytes(n, 50 * m, "balanced", False) < lbgmod.workspace_bytes(n, 50 * m, "edge", False) / 10
     # invalid arguments
@@ -89,7 +96,8 @@ def _sssp(n=10, m=20, src=0, weights=FAKE, strategy=lbgmod.BALANCED, coo=None, w
     (dict(out=None), lbgmod.EINVAL),
     (dict(ws=None), lbgmod.EINVAL),
     (dict(cols=None), lbgmod.EINVAL),
-    (dict(strategy=7), lbgmod.EINVAL),
+    (dict(strategy=8), lbgmod.EINVAL),
+    (dict(strategy=lbgmod.SLICED), lbgmod.EINVAL),        # only through lbg_bfs_sliced
     (dict(strategy=-2), lbgmod.EINVAL),
     (dict(strategy=lbgmod.EDGE_NOCHUNK), lbgmod.EINVAL),  # no coo_src
     (dict(strategy=lbgmod.EDGE), lbgmod.EINVAL),          # no coo_src
@@ -158,3 +166,43 @@ def test_bins_validation_and_round_trip():
     out = ctypes.c_int32(0)
     assert lib.lbg_degree_mdt(FAKE, 0, 5, WS, 1 << 20, ctypes.byref(out), None, None) == lbgmod.EINVAL
     assert lib.lbg_degree_mdt(FAKE, 5, 5, WS, 8, ctypes.byref(out), None, None) == lbgmod.ENOMEM
+
+
+def test_slice_min_setting():
+    saved = lbgmod.get_slice_min()
+    with pytest.raises(lbgmod.LbgError):
+        lbgmod.set_slice_min(-1)
+    assert lbgmod.get_slice_min() == saved
+    lbgmod.set_slice_min(0)
+    assert lbgmod.get_slice_min() == 0
+    lbgmod.set_slice_min(2**31 - 1)
+    assert lbgmod.get_slice_min() == 2**31 - 1
+    lbgmod.set_slice_min(saved)
+
+
+def test_slice_sizes():
+    for n, S in ((1, 64), (8, 64), (512, 64), (513, 128), (4194304, 524288), (1000, 128)):
+        assert lbgmod.slice_nodes(n) == S
+        assert 8 * S >= n and S % 64 == 0
+    assert lbgmod.slice_nodes(0) == 0
+
+
+def test_sliced_argument_errors():
+    def grp(n=10, m=20, offsets=FAKE, cols=FAKE, w=FAKE, so=FAKE, cout=FAKE, wout=FAKE):
+        return lib.lbg_slice_graph(offsets, cols, w, n, m, so, cout, wout, None)
+
+    assert grp(n=0) == lbgmod.EINVAL
+    assert grp(m=-1) == lbgmod.ERANGE
+    assert grp(m=2**31) == lbgmod.ERANGE
+    assert grp(offsets=None) == lbgmod.EINVAL
+    assert grp(so=None) == lbgmod.EINVAL
+    assert grp(cout=None) == lbgmod.EINVAL
+    assert grp(wout=None) == lbgmod.EINVAL   # weights without weights_out
+    assert grp(w=None) == lbgmod.EINVAL      # weights_out without weights
+    ws = 1 << 40
+    assert lib.lbg_bfs_sliced(FAKE, FAKE, FAKE, 10, 20, 10, FAKE, WS, ws, None, None) == lbgmod.ERANGE
+    assert lib.lbg_bfs_sliced(FAKE, FAKE, FAKE, 0, 20, 0, FAKE, WS, ws, None, None) == lbgmod.EINVAL
+    assert lib.lbg_bfs_sliced(FAKE, FAKE, FAKE, 10, 20, 0, FAKE, WS, 64, None, None) == lbgmod.ENOMEM
+    assert lib.lbg_bfs_sliced(FAKE, None, FAKE, 10, 20, 0, FAKE, WS, ws, None, None) == lbgmod.EINVAL
+    assert lib.lbg_sssp_sliced(FAKE, FAKE, FAKE, None, 10, 20, 0, FAKE, WS, ws, None, None) == lbgmod.EINVAL
+    assert lib.lbg_sssp_sliced(None, FAKE, FAKE, FAKE, 10, 20, 0, FAKE, WS, ws, None, None) == lbgmod.EINVAL

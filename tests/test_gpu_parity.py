@@ -16,8 +16,8 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 from paper_1711_00231_amd import lbg  # noqa: E402  (fails loudly if liblbg.so is missing)
 
-STRATS = ["node", "edge", "balanced", "binned", "hier", "edge_nochunk"]
-FULL_STRATS = ["node", "edge", "balanced", "binned", "hier"]  # the ablation is too slow at full size
+STRATS = ["node", "edge", "balanced", "binned", "hier", "edge_nochunk", "sliced"]
+FULL_STRATS = ["node", "edge", "balanced", "binned", "hier", "sliced"]  # the ablation is too slow at full size
 O = oracle.get()
 
 
@@ -221,6 +221,63 @@ def test_tuned_bins_cache_round_trip(tmp_path):
         lbg.set_bins(**saved)
 
 
+@pytest.mark.parametrize("smin", [0, 1, 7, 2**31 - 1])
+def test_sliced_thresholds(smin):
+    """Every node split by slice (0, 1), small nodes mixed (7), no node split
+    (INT32_MAX): the same results."""
+    saved = lbg.get_slice_min()
+    try:
+        lbg.set_slice_min(smin)
+        g = graphgen.rmat(14)
+        _check(g, _dev(g), graphgen.sources(g, 2, graphgen.FAMILY_RMAT), "sliced")
+        for gg, s in pins.tiny_graphs(count=10, seed=5):
+            _check(gg, _dev(gg), [s], "sliced")
+        h = graphgen.grid(48)
+        _check(h, _dev(h), [0], "sliced")
+    finally:
+        lbg.set_slice_min(saved)
+
+
+def _expected_slicing(g):
+    S = lbg.slice_nodes(g.n)
+    row = np.repeat(np.arange(g.n), g.degrees)
+    sl = np.minimum(g.cols.astype(np.int64) // S, 7)
+    order = np.lexsort((sl, row))  # by node, then slice; stable within a slice
+    cnt = np.zeros((g.n, 8), np.int64)
+    np.add.at(cnt, (row, sl), 1)
+    first = g.offsets[:-1, None].astype(np.int64) + np.cumsum(cnt, axis=1) - cnt
+    return order, np.concatenate([first.ravel(), [g.m]])
+
+
+@pytest.mark.parametrize("which", ["uniform", "rmat", "hub", "tiny"])
+def test_slice_graph_groups_adjacency(which):
+    """lbg_slice_graph regroups every adjacency list by destination slice,
+    keeping the input order within a slice (compared with a stable sort),
+    and its slice offsets are the per-node slice prefix sums."""
+    rng = np.random.default_rng(3)
+    if which == "uniform":
+        g = graphgen.uniform(13)          # unsorted adjacency lists
+    elif which == "rmat":
+        g = graphgen.rmat(14)
+    elif which == "hub":
+        n = 5000
+        src = np.concatenate([np.zeros(4000, np.int64), rng.integers(0, n, 9000)])
+        dst = rng.integers(0, n, src.size)
+        g = graphgen.from_edges(n, src, dst, rng.integers(1, 9, src.size), "hub")
+    else:
+        g = graphgen.from_edges(3, [0, 0, 2], [2, 1, 0], [5, 6, 7], "tiny")
+    dg = _dev(g)
+    sg = lbg.slice_graph(dg)
+    order, exp_so = _expected_slicing(g)
+    assert np.array_equal(sg.slice_offsets.cpu().numpy().astype(np.int64), exp_so)
+    assert np.array_equal(sg.cols.cpu().numpy()[: g.m], g.cols[order])
+    assert np.array_equal(sg.weights.cpu().numpy().view(np.uint32)[: g.m], g.weights[order])
+    # BFS-only graphs: no weights in, none out
+    bg = lbg.DeviceGraph(dg.offsets, dg.cols, None)
+    sb = lbg.slice_graph(bg)
+    assert sb.weights is None and np.array_equal(sb.cols.cpu().numpy()[: g.m], g.cols[order])
+
+
 def test_repeat_runs_identical():
     """Relaxation order differs from run to run; results must not."""
     g = graphgen.rmat(14)
@@ -245,6 +302,26 @@ def test_stats_and_validate():
         assert st["edges_scanned"] == g.reached_arcs(reached)
         assert st["updates"] == int(reached.sum()) - 1
         assert st["frontier_entries"] == int((reached & (g.degrees > 0)).sum())
+    # sliced: one entry per (node, destination slice it has arcs into) for
+    # nodes of degree >= slice_min, one entry for the others
+    S = lbg.slice_nodes(g.n)
+    row = np.repeat(np.arange(g.n), g.degrees)
+    pairs = np.unique(row.astype(np.int64) * 8 + np.minimum(g.cols // S, 7))
+    per_node = np.bincount(pairs // 8, minlength=g.n)
+    saved = lbg.get_slice_min()
+    try:
+        for smin in (0, 16, 2**31 - 1):
+            lbg.set_slice_min(smin)
+            lv, st = _gpu_bfs(dg, s, "sliced", stats=True)
+            assert np.array_equal(lv, lv_exp)
+            assert st["levels"] == int(lv_exp[reached].max()) + 1
+            assert st["edges_scanned"] == g.reached_arcs(reached)
+            assert st["updates"] == int(reached.sum()) - 1
+            split = g.degrees >= smin
+            exp_entries = per_node[reached & split].sum() + (reached & ~split & (g.degrees > 0)).sum()
+            assert st["frontier_entries"] == int(exp_entries), smin
+    finally:
+        lbg.set_slice_min(saved)
     d, st = _gpu_sssp(dg, s, "balanced", stats=True)
     assert st["edges_scanned"] >= g.reached_arcs(reached)
     lbg.validate_csr(dg)
