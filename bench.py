@@ -91,7 +91,8 @@ def recorded_traffic():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("paper_1711_00231_amd/csrc/lbg_kernels.hpp", "paper_1711_00231_amd/csrc/lbg_device.hpp"):
+    for f in ("paper_1711_00231_amd/csrc/lbg_kernels.hpp", "paper_1711_00231_amd/csrc/lbg_device.hpp",
+              "paper_1711_00231_amd/csrc/lbg_sliced.hpp"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     out = {}
@@ -142,7 +143,8 @@ def run_plain(args, lbg, torch, dev):
     g, srcs, desc, sym = make_workload(args.workload)
     log(f"workload {g.name}: n={g.n} m={g.m} built in {time.perf_counter() - t0:.1f}s")
     dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev,
-                                    with_coo=(args.strategy == "edge"))
+                                    with_coo=(args.strategy in ("edge", "edge_nochunk")),
+                                    with_slices=(args.strategy == "sliced"))
     ws = lbg.Workspace(dev)
     lv_out = torch.empty(g.n, dtype=torch.int32, device=dev)
     d_out = torch.empty(g.n, dtype=torch.int32, device=dev)
@@ -261,14 +263,16 @@ def run_plain(args, lbg, torch, dev):
 # ----------------------------------------------------------- strategies --
 def run_strategies(lbg, torch, g, srcs, dev):
     """Node-based vs edge-based vs hierarchical vs balanced vs degree-binned
-    assignment on the same graph: BFS and SSSP from two sources each (binned
-    with bins autotuned on two other sources)."""
-    dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev, with_coo=True)
+    vs destination-sliced assignment on the same graph: BFS and SSSP from two
+    sources each (binned with bins autotuned on two other sources; the
+    sliced graph and the COO array are built before timing)."""
+    dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev, with_coo=True,
+                                    with_slices=True)
     deg = g.degrees
     tuned = lbg.autotune_bins(dg, [int(x) for x in srcs[2:4]])
     ws = lbg.Workspace(dev)
-    out = {"bins": tuned}
-    for strat in ("node", "edge", "hier", "balanced", "binned"):
+    out = {"bins": tuned, "slice_min": lbg.get_slice_min()}
+    for strat in ("node", "edge", "hier", "balanced", "binned", "sliced"):
         res = {}
         for kind, f in (("bfs", lbg.bfs), ("sssp", lbg.sssp)):
             ts, arcs = [], 0
