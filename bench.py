@@ -216,6 +216,7 @@ def run_plain(args, lbg, torch, dev):
         "data": "synthetic",
         "config": {"workload": desc, "graph": g.name, "n": g.n, "m": g.m,
                    "sources_per_step": per, "strategy": args.strategy,
+                   **({"slice_min": lbg.get_slice_min()} if args.strategy == "sliced" else {}),
                    "solves_timed": 2 * n_solves},
         "bfs_gteps": round(bfs_arcs / (bfs_ms / 1e3) / 1e9, 4),
         "sssp_gteps": round(bfs_arcs / (sssp_ms / 1e3) / 1e9, 4),
@@ -472,6 +473,8 @@ def main():
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--strategy", default="balanced")
+    ap.add_argument("--slice-min", type=int, default=None,
+                    help="split degree of the sliced strategy (lbg_set_slice_min)")
     ap.add_argument("--sources-per-step", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the cpu_baseline leg (0 = skip)")
@@ -496,6 +499,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.slice_min is not None:
+        lbg.set_slice_min(args.slice_min)
 
     if args.mode == "batch":
         res = run_batch(lbg, torch, dev, count=256, sources_per_instance=4, hi_exp=18)
