@@ -146,6 +146,30 @@ int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weight
              int32_t strategy, const int32_t* coo_src, lbg_stats* stats, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Packed arcs for SSSP (the balanced strategy of Section III-A on a denser
+ * arc encoding).
+ *
+ * lbg_pack_arcs: arcs_out[e] = (cols[e] << wbits) | weights[e], with wbits
+ * the bit length of the largest weight (0 if all weights are 0), written to
+ * *wbits_out.  Needs bitlength(n - 1) + wbits <= 32, else LBG_ERANGE (e.g.
+ * n = 2^22 nodes with weights below 256, or n = 2^24 with weights below
+ * 256).  workspace: device scratch of at least 1152 bytes (the control
+ * block; any solve workspace will do), 256-byte aligned, overwritten.  cols must lie in [0, n)
+ * (lbg_validate_csr).  Returns when arcs_out is written.
+ *
+ * lbg_sssp_packed: lbg_sssp with strategy LBG_BALANCED reading arc e as one
+ * 32-bit word of arcs[] instead of cols[e] and weights[e] (one load per arc
+ * instead of two, half the arc bytes); same offsets, same workspace
+ * (lbg_workspace_bytes(n, m, LBG_BALANCED, 1)), identical results.
+ * LBG_ERANGE if wbits is outside [0, 31] or the node ids of n do not fit
+ * beside wbits weight bits. */
+int lbg_pack_arcs(const int32_t* cols, const uint32_t* weights, int32_t n, int64_t m, uint32_t* arcs_out,
+                  int32_t* wbits_out, void* workspace, size_t workspace_bytes, void* stream);
+int lbg_sssp_packed(const int32_t* offsets, const uint32_t* arcs, int32_t wbits, int32_t n, int64_t m,
+                    int32_t src, uint32_t* dist_out, void* workspace, size_t workspace_bytes,
+                    lbg_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
  * Destination-sliced graphs (LBG_SLICED; the workload decomposition of
  * Section III-A, cut per destination slice).
  *

@@ -135,6 +135,8 @@ int resident_grid(K kernel) {
 struct Grids {
   int bal[2][2], node[2], edge[2], edge_nc[2], multi[2], binned[2], hier[2];  // bal[is_sssp][narrow], multi[narrow]
   int sliced[2][2];                                      // [is_sssp][narrow], a multiple of 8 (>= 8)
+  int bal_p[2];                                          // SSSP with packed arcs [narrow]
+  bool small_p[2];
   bool small[2][2];                                      // small-frontier kernel fits the device
 };
 
@@ -179,6 +181,10 @@ const Grids& grids() {
     g[dev].binned[1] = resident_grid(lbg::k_expand_binned<true>);
     g[dev].multi[0] = resident_grid(lbg::k_expand_balanced<true, false, true>);
     g[dev].multi[1] = resident_grid(lbg::k_expand_balanced<true, true, true>);
+    g[dev].bal_p[0] = resident_grid(lbg::k_expand_balanced<true, false, false, true>);
+    g[dev].bal_p[1] = resident_grid(lbg::k_expand_balanced<true, true, false, true>);
+    g[dev].small_p[0] = fits_lds(lbg::k_expand_small<true, false, true>);
+    g[dev].small_p[1] = fits_lds(lbg::k_expand_small<true, true, true>);
     g[dev].sliced[0][0] = slice_grid(resident_grid(lbg::k_expand_sliced<false, false>));
     g[dev].sliced[0][1] = slice_grid(resident_grid(lbg::k_expand_sliced<false, true>));
     g[dev].sliced[1][0] = slice_grid(resident_grid(lbg::k_expand_sliced<true, false>));
@@ -274,6 +280,8 @@ struct Problem {
   hipStream_t stream;
   bool sliced = false;           // called through lbg_bfs_sliced / lbg_sssp_sliced
   const int32_t* soff = nullptr;  // their slice offsets
+  const uint32_t* arcs = nullptr; // lbg_sssp_packed: packed arcs (cols/weights unused)
+  int32_t wbits = 0;
 };
 
 int check_common(const Problem& P) {
@@ -283,13 +291,19 @@ int check_common(const Problem& P) {
     return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(P.m));
   if (P.src < 0 || P.src >= P.n) return fail(LBG_ERANGE, "src %d outside [0, %d)", P.src, P.n);
   if (!P.offsets || !P.out || !P.ws) return fail(LBG_EINVAL, "null offsets/output/workspace pointer");
-  if (P.m > 0 && !P.cols) return fail(LBG_EINVAL, "null cols pointer with m > 0");
-  if (P.is_sssp && P.m > 0 && !P.weights) return fail(LBG_EINVAL, "null weights pointer with m > 0");
+  if (P.m > 0 && !P.cols) return fail(LBG_EINVAL, "null cols (or packed arcs) pointer with m > 0");
+  if (P.is_sssp && P.m > 0 && !P.weights) return fail(LBG_EINVAL, "null weights (or packed arcs) pointer with m > 0");
   if (edge_wl(resolve(P.strategy)) && !P.coo_src)
     return fail(LBG_EINVAL, "LBG_EDGE needs the coo_src array");
   if ((resolve(P.strategy) == LBG_SLICED) != P.sliced)
     return fail(LBG_EINVAL, "LBG_SLICED runs through lbg_bfs_sliced / lbg_sssp_sliced only");
   if (P.sliced && !P.soff) return fail(LBG_EINVAL, "null slice_offsets pointer");
+  if (P.arcs) {
+    if (P.wbits < 0 || P.wbits > 31)
+      return fail(LBG_ERANGE, "wbits must be in [0, 31] (got %d)", P.wbits);
+    if (P.wbits > 0 && (static_cast<uint64_t>(P.n - 1) >> (32 - P.wbits)) != 0)
+      return fail(LBG_ERANGE, "node ids of n = %d do not fit beside %d weight bits", P.n, P.wbits);
+  }
   if (reinterpret_cast<uintptr_t>(P.ws) % kAlign)
     return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
   const size_t need = layout(P.n, P.m, P.strategy, P.is_sssp).total;
@@ -310,6 +324,9 @@ int solve(const Problem& P) {
   a.cols = P.cols;
   a.weights = P.weights;
   a.coo_src = P.coo_src;
+  a.arcs = P.arcs;
+  a.wbits = static_cast<uint32_t>(P.wbits);
+  const bool packed = P.arcs != nullptr;
   if (P.is_sssp) {
     a.dist = static_cast<uint32_t*>(P.out);
     a.dstate = reinterpret_cast<unsigned long long*>(ws + Lay.dstate);
@@ -417,8 +434,14 @@ int solve(const Problem& P) {
             hipLaunchKernelGGL((lbg::k_expand_hier<true>), dim3(GR.hier[sv]), dim3(lbg::kBlock), 0, st, a, L, k, hier_mdt);
           break;
         default:
-          if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
-          else hipLaunchKernelGGL((lbg::k_expand_balanced<true, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          if (packed) {
+            if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true, false, true>), dim3(GR.bal_p[nw]), dim3(lbg::kBlock), 0, st, a, L);
+            else hipLaunchKernelGGL((lbg::k_expand_balanced<true, false, false, true>), dim3(GR.bal_p[nw]), dim3(lbg::kBlock), 0, st, a, L);
+          } else if (narrow) {
+            hipLaunchKernelGGL((lbg::k_expand_balanced<true, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          } else {
+            hipLaunchKernelGGL((lbg::k_expand_balanced<true, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          }
           break;
       }
     } else {
@@ -451,7 +474,7 @@ int solve(const Problem& P) {
   // levels to the single-workgroup kernel, which keeps going on the device
   // until a level outgrows those limits or the worklist empties; the host
   // then resumes from ctl->levels, the next level to expand.
-  const bool small_ok = strat == LBG_BALANCED && GR.small[sv][nw];
+  const bool small_ok = strat == LBG_BALANCED && (packed ? GR.small_p[nw] : GR.small[sv][nw]);
   uint32_t L = 0, L_prev = 0;
   uint32_t batch = 8;
   bool small = false;
@@ -468,7 +491,10 @@ int solve(const Problem& P) {
     if (small) {
       if (profiling && (rc = mark()) != LBG_OK) return rc;
       const uint32_t max_levels = static_cast<uint32_t>(level_cap + 1 - L);
-      if (P.is_sssp) {
+      if (P.is_sssp && packed) {
+        if (narrow) hipLaunchKernelGGL((lbg::k_expand_small<true, true, true>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
+        else hipLaunchKernelGGL((lbg::k_expand_small<true, false, true>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
+      } else if (P.is_sssp) {
         if (narrow) hipLaunchKernelGGL((lbg::k_expand_small<true, true>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
         else hipLaunchKernelGGL((lbg::k_expand_small<true, false>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
       } else {
@@ -1165,6 +1191,54 @@ int lbg_slice_graph(const int32_t* offsets, const int32_t* cols, const uint32_t*
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return LBG_OK;
+}
+
+int lbg_pack_arcs(const int32_t* cols, const uint32_t* weights, int32_t n, int64_t m, uint32_t* arcs_out,
+                  int32_t* wbits_out, void* workspace, size_t workspace_bytes, void* stream) {
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX)
+    return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
+  if (!wbits_out || !workspace || (m > 0 && (!cols || !weights || !arcs_out)))
+    return fail(LBG_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  if (workspace_bytes < sizeof(Ctl)) return fail(LBG_ENOMEM, "workspace smaller than %zu bytes", sizeof(Ctl));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ctl* ctl = static_cast<Ctl*>(workspace);
+  Ctl* host = pinned_ctl();
+  if (!host) return fail(LBG_EHIP, "hipHostMalloc of the readback word failed");
+  const int blocks = static_cast<int>(
+      std::min<int64_t>(std::max<int64_t>((m + lbg::kBlock - 1) / lbg::kBlock, 1), 4096));
+  hipLaunchKernelGGL(lbg::k_deg_clear, dim3(1), dim3(lbg::kBlock), 0, st, ctl);
+  if (m > 0)
+    hipLaunchKernelGGL(lbg::k_weight_max, dim3(blocks), dim3(lbg::kBlock), 0, st, weights, static_cast<uint32_t>(m), ctl);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const uint32_t wmax = host->deg_max;
+  int32_t wbits = 0;
+  while (wbits < 32 && (wmax >> wbits) != 0u) ++wbits;
+  if (wbits > 31 || (wbits > 0 && (static_cast<uint64_t>(n - 1) >> (32 - wbits)) != 0))
+    return fail(LBG_ERANGE, "n = %d node ids and weights up to %u do not fit in 32 bits", n, wmax);
+  if (m > 0)
+    hipLaunchKernelGGL(lbg::k_pack_arcs, dim3(blocks), dim3(lbg::kBlock), 0, st, cols, weights,
+                       static_cast<uint32_t>(m), static_cast<uint32_t>(wbits), arcs_out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  *wbits_out = wbits;
+  return LBG_OK;
+}
+
+int lbg_sssp_packed(const int32_t* offsets, const uint32_t* arcs, int32_t wbits, int32_t n, int64_t m,
+                    int32_t src, uint32_t* dist_out, void* workspace, size_t workspace_bytes,
+                    lbg_stats* stats, void* stream) {
+  // any stray read of cols/weights stays inside the arc array
+  Problem P{offsets, reinterpret_cast<const int32_t*>(arcs), arcs, nullptr, n, m, src, dist_out, workspace,
+            workspace_bytes, LBG_BALANCED, 1, stats, static_cast<hipStream_t>(stream)};
+  P.arcs = arcs;
+  P.wbits = wbits;
+  if (m > 0 && !arcs) return fail(LBG_EINVAL, "null arcs pointer with m > 0");
+  return solve(P);
 }
 
 int lbg_set_slice_min(int32_t min_degree) {

@@ -97,6 +97,10 @@ struct KArgs {
   uint32_t* xfilter;     // BFS: per-XCD advisory copy of `visited`, kXcds x words
   unsigned long long* dstate;  // SSSP: (distance << 32) | iteration of last improvement
   uint16_t* d16;         // SSSP single solves: filter, min(an upper bound of the distance, 0xffff)
+  // Packed arcs (SSSP, balanced): arc e = (cols[e] << wbits) | weights[e],
+  // one 32-bit load per arc instead of two.
+  const uint32_t* arcs;
+  uint32_t wbits;
   Frontier fr[2];
   int32_t* sub[2];       // hierarchical strategy: sublists (worklist indices) of two sub-iterations
   Ctl* ctl;

@@ -44,6 +44,20 @@ namespace lbg {
 constexpr uint32_t kBfsInf = 0x7fffffffu;
 constexpr uint32_t kSsspInf = 0xffffffffu;
 
+// Arc e of a single SSSP solve: destination and weight, from the CSR arrays
+// or from one packed word.
+template <bool kPacked, bool kNarrow>
+__device__ __forceinline__ void load_arc(const KArgs& a, uint32_t e, int32_t* v, uint32_t* w) {
+  if (kPacked) {
+    const uint32_t pa = *at<kNarrow>(a.arcs, e);
+    *v = static_cast<int32_t>(pa >> a.wbits);
+    *w = pa & ((1u << a.wbits) - 1u);
+  } else {
+    *v = *at<kNarrow>(a.cols, e);
+    *w = *at<kNarrow>(a.weights, e);
+  }
+}
+
 
 // Level bookkeeping, by one thread of the grid: clear the counter two levels
 // ahead (the one level L+1 appends to) and account level L.  kSmall: the
@@ -299,9 +313,10 @@ __device__ __forceinline__ bool level_fits(const KArgs& a, unsigned long long c)
 // One level of the balanced expansion by the whole grid (all threads of
 // every block must call it).  c = the level's packed tail, non-empty and
 // within capacity.
-template <bool kSssp, bool kNarrow, bool kMulti>
+template <bool kSssp, bool kNarrow, bool kMulti, bool kPacked = false>
 __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigned long long c) {
   static_assert(!kMulti || kSssp, "batched solves use the SSSP relaxation");
+  static_assert(!kPacked || (kSssp && !kMulti), "packed arcs: single SSSP solves");
   constexpr int kItems = TileCfg<kSssp, kMulti>::kItems;
   constexpr uint32_t T = TileCfg<kSssp, kMulti>::kEdges;
   constexpr int kPay = kMulti ? 2 : (kSssp ? 1 : 0);
@@ -432,7 +447,11 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
         if (kSssp && slot >= 0 && w.du[slot] == kSsspInf) {
           // skipped entry (see staging)
         } else if (e < a.m) {
-          vv[r] = *at<kNarrow>(a.cols, e);
+          if (kPacked) {
+            load_arc<true, kNarrow>(a, e, &vv[r], &ww[r]);
+          } else {
+            vv[r] = *at<kNarrow>(a.cols, e);
+          }
           if (kSssp) {
             du[r] = w.du[slot];
             if (kMulti) {
@@ -443,7 +462,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
                   static_cast<uint32_t>(vv[r] - w.lo[slot]) < (lk & 0x7fffffffu);
               bfsq[kMulti ? r : 0] = !(lk >> 31);
               ww[r] = (lk >> 31) ? *at<kNarrow>(a.weights, e) : 1u;
-            } else {
+            } else if (!kPacked) {
               ww[r] = *at<kNarrow>(a.weights, e);
             }
           }
@@ -584,7 +603,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   add_stats(a, upd, atom);
 }
 
-template <bool kSssp, bool kNarrow, bool kMulti>
+template <bool kSssp, bool kNarrow, bool kMulti, bool kPacked = false>
 __device__ __forceinline__ void balanced_level(const KArgs& a, uint32_t L) {
   const unsigned long long c = level_begin(a, L);
   if (static_cast<uint32_t>(c) == 0u) return;
@@ -592,12 +611,12 @@ __device__ __forceinline__ void balanced_level(const KArgs& a, uint32_t L) {
     if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrNodeCap);
     return;
   }
-  expand_level<kSssp, kNarrow, kMulti>(a, L, c);
+  expand_level<kSssp, kNarrow, kMulti, kPacked>(a, L, c);
 }
 
-template <bool kSssp, bool kNarrow, bool kMulti = false>
+template <bool kSssp, bool kNarrow, bool kMulti = false, bool kPacked = false>
 __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
-  balanced_level<kSssp, kNarrow, kMulti>(a, L);
+  balanced_level<kSssp, kNarrow, kMulti, kPacked>(a, L);
 }
 
 // Graph-launched batches: one replay of a graph runs levels level_base + k
@@ -727,8 +746,9 @@ __device__ __forceinline__ unsigned long long small_overflow(const KArgs& a, Sma
   return (static_cast<unsigned long long>(cnt) << 32) | base_e;
 }
 
-template <bool kSssp, bool kNarrow>
+template <bool kSssp, bool kNarrow, bool kPacked = false>
 __global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t L0, uint32_t max_levels) {
+  static_assert(!kPacked || kSssp, "packed arcs: SSSP");
   constexpr uint32_t T = TileCfg<kSssp>::kEdges;
   constexpr int kPay = kSssp ? 1 : 0;
   __shared__ SmallLds<kSssp> sm;
@@ -802,11 +822,13 @@ __global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t 
           const uint32_t i = sm.wpre[k] + __popc(sm.flag[k] & msk) - 1;  // entry 0 starts at slot 0
           const uint32_t arc = sm.s[i] + (e - sm.p[i]);
           if (i < nf && arc < a.m) {
-            vv[r] = *at<kNarrow>(a.cols, arc);
-            if (kSssp) {
-              ww[r] = *at<kNarrow>(a.weights, arc);
-              du[r] = sm.du[i];
+            if (kPacked) {
+              load_arc<true, kNarrow>(a, arc, &vv[r], &ww[r]);
+            } else {
+              vv[r] = *at<kNarrow>(a.cols, arc);
+              if (kSssp) ww[r] = *at<kNarrow>(a.weights, arc);
             }
+            if (kSssp) du[r] = sm.du[i];
           } else {
             bad = true;
           }
@@ -1533,6 +1555,22 @@ __global__ __launch_bounds__(kBlock) void k_validate(const int32_t* offsets, con
   for (uint32_t e = gid; e < m; e += stride)
     if (cols[e] < 0 || static_cast<uint32_t>(cols[e]) >= n) flags |= 8u;
   if (flags) atomicOr(&ctl->csr_flags, flags);
+}
+
+// ------------------------------------------------------- packed arcs --
+// Largest weight (into ctl->deg_max), then the packed words
+// (cols[e] << wbits) | weights[e].
+__global__ __launch_bounds__(kBlock) void k_weight_max(const uint32_t* weights, uint32_t m, Ctl* ctl) {
+  uint32_t mx = 0u;
+  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < m; e += gridDim.x * kBlock) mx = max(mx, weights[e]);
+  mx = static_cast<uint32_t>(wave_max(static_cast<int32_t>(mx ^ 0x80000000u))) ^ 0x80000000u;  // unsigned max
+  if (lane_id() == 0 && mx) atomicMax(&ctl->deg_max, mx);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_arcs(const int32_t* cols, const uint32_t* weights, uint32_t m,
+                                                      uint32_t wbits, uint32_t* arcs) {
+  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < m; e += gridDim.x * kBlock)
+    arcs[e] = (static_cast<uint32_t>(cols[e]) << wbits) | weights[e];
 }
 
 }  // namespace lbg

@@ -77,6 +77,10 @@ def _load():
     lib.lbg_sssp.restype = ctypes.c_int
     lib.lbg_sssp.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, sz, i32, vp,
                              ctypes.POINTER(Stats), vp]
+    lib.lbg_pack_arcs.restype = ctypes.c_int
+    lib.lbg_pack_arcs.argtypes = [vp, vp, i32, i64, vp, ctypes.POINTER(i32), vp, sz, vp]
+    lib.lbg_sssp_packed.restype = ctypes.c_int
+    lib.lbg_sssp_packed.argtypes = [vp, vp, i32, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
     lib.lbg_slice_nodes.restype = i32
     lib.lbg_slice_nodes.argtypes = [i32]
     lib.lbg_set_slice_min.restype = ctypes.c_int
@@ -178,6 +182,7 @@ class DeviceGraph:
     coo_src: torch.Tensor | None = None
     host_offsets: object = None  # numpy copy, used to size batched solves
     sliced: "SlicedGraph | None" = None
+    packed: "tuple | None" = None  # (arcs tensor, wbits) from lbg_pack_arcs
 
     @property
     def n(self) -> int:
@@ -188,7 +193,8 @@ class DeviceGraph:
         return int(self.cols.numel())
 
     @classmethod
-    def from_numpy(cls, offsets, cols, weights=None, device="cuda", with_coo=False, with_slices=False):
+    def from_numpy(cls, offsets, cols, weights=None, device="cuda", with_coo=False, with_slices=False,
+                   with_packed=False):
         import numpy as np
 
         off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.int32)).to(device)
@@ -201,7 +207,25 @@ class DeviceGraph:
             g.ensure_coo()
         if with_slices:
             g.ensure_sliced()
+        if with_packed:
+            g.ensure_packed()
         return g
+
+    def ensure_packed(self, stream=None) -> tuple:
+        """(arcs, wbits): arc e as one word (cols[e] << wbits) | weights[e]
+        (lbg_pack_arcs); raises LbgError(ERANGE) if ids and weights do not
+        fit in 32 bits."""
+        if self.packed is None:
+            if self.weights is None:
+                raise ValueError("packing needs weights")
+            dev = self.offsets.device
+            arcs = torch.empty(max(self.m, 1), dtype=torch.int32, device=dev)
+            scratch = _ws(None, 4096, dev)
+            wb = ctypes.c_int32(0)
+            _check(lib.lbg_pack_arcs(_ptr(self.cols), _ptr(self.weights), self.n, self.m, _ptr(arcs),
+                                     ctypes.byref(wb), _ptr(scratch), scratch.numel(), _stream(stream)))
+            self.packed = (arcs, int(wb.value))
+        return self.packed
 
     def ensure_sliced(self, stream=None) -> "SlicedGraph":
         if self.sliced is None:
@@ -301,10 +325,13 @@ def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None 
 
 
 def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None = None,
-         workspace: Workspace | None = None, stats: bool = False, stream=None):
+         workspace: Workspace | None = None, stats: bool = False, stream=None, packed: bool = False):
     """Distances from ``src`` as an int32 tensor holding uint32 bit patterns
-    (use ``.view(torch.uint32)``; UINT32_MAX = unreachable)."""
+    (use ``.view(torch.uint32)``; UINT32_MAX = unreachable).  ``packed``:
+    balanced strategy on the packed arc words (lbg_sssp_packed)."""
     s = _strategy(strategy)
+    if packed and s not in (AUTO, BALANCED):
+        raise ValueError("packed arcs run the balanced strategy")
     if g.weights is None:
         raise ValueError("sssp needs weights")
     if out is None:
@@ -313,7 +340,11 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
-    if s == SLICED:
+    if packed:
+        arcs, wbits = g.ensure_packed(stream)
+        rc = lib.lbg_sssp_packed(_ptr(g.offsets), _ptr(arcs), wbits, g.n, g.m, int(src), _ptr(out), _ptr(ws),
+                                 ws.numel(), ctypes.byref(st) if stats else None, _stream(stream))
+    elif s == SLICED:
         sg = g.ensure_sliced(stream)
         if sg.weights is None:
             raise ValueError("the sliced graph was built without weights")

@@ -206,3 +206,25 @@ def test_sliced_argument_errors():
     assert lib.lbg_bfs_sliced(FAKE, None, FAKE, 10, 20, 0, FAKE, WS, ws, None, None) == lbgmod.EINVAL
     assert lib.lbg_sssp_sliced(FAKE, FAKE, FAKE, None, 10, 20, 0, FAKE, WS, ws, None, None) == lbgmod.EINVAL
     assert lib.lbg_sssp_sliced(None, FAKE, FAKE, FAKE, 10, 20, 0, FAKE, WS, ws, None, None) == lbgmod.EINVAL
+
+
+def test_packed_argument_errors():
+    wb = ctypes.c_int32(0)
+    pk = lambda n=10, m=20, cols=FAKE, w=FAKE, out=FAKE, wbo=ctypes.byref(wb), ws=WS, wsb=1 << 20: \
+        lib.lbg_pack_arcs(cols, w, n, m, out, wbo, ws, wsb, None)
+    assert pk(n=0) == lbgmod.EINVAL
+    assert pk(m=-1) == lbgmod.ERANGE
+    assert pk(cols=None) == lbgmod.EINVAL
+    assert pk(w=None) == lbgmod.EINVAL
+    assert pk(out=None) == lbgmod.EINVAL
+    assert pk(wbo=None) == lbgmod.EINVAL
+    assert pk(ws=ctypes.c_void_p(0x10010)) == lbgmod.EINVAL
+    assert pk(wsb=64) == lbgmod.ENOMEM
+    sp = lambda n=10, m=20, arcs=FAKE, wbits=4, src=0, wsb=1 << 40: \
+        lib.lbg_sssp_packed(FAKE, arcs, wbits, n, m, src, FAKE, WS, wsb, None, None)
+    assert sp(wbits=32) == lbgmod.ERANGE
+    assert sp(wbits=-1) == lbgmod.ERANGE
+    assert sp(n=1 << 29, wbits=4) == lbgmod.ERANGE   # 29 id bits + 4 weight bits
+    assert sp(arcs=None) == lbgmod.EINVAL
+    assert sp(src=10) == lbgmod.ERANGE
+    assert sp(wsb=16) == lbgmod.ENOMEM

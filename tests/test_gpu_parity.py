@@ -238,6 +238,61 @@ def test_sliced_thresholds(smin):
         lbg.set_slice_min(saved)
 
 
+def _packed_cases():
+    rng = np.random.default_rng(11)
+    n = 20000
+    hub_src = np.concatenate([np.zeros(7 * 512 + 13, np.int64), rng.integers(1, n, 30000)])
+    hub = graphgen.from_edges(n, hub_src, rng.integers(0, n, hub_src.size), rng.integers(1, 50, hub_src.size), "hub")
+    return [
+        (graphgen.from_edges(1, [], [], [], "single-node"), [0]),
+        (graphgen.from_edges(5, [1, 2], [2, 3], [4, 5], "isolated-source"), [0, 1]),
+        (graphgen.from_edges(3, [0, 0, 0, 1], [0, 1, 1, 1], [3, 7, 2, 0], "loops-and-dups"), [0]),
+        (graphgen.from_edges(4, [0, 1, 2], [1, 2, 3], [0, 0, 0], "zero-weights"), [0]),  # wbits = 0
+        (pins.path_graph(3000, np.full(2999, 7)), [0]),
+        (hub, [0, 1, 17]),
+        (graphgen.uniform(14), [0, 1234]),
+        (graphgen.rmat(15), list(graphgen.sources(graphgen.rmat(15), 2, graphgen.FAMILY_RMAT))),
+        (graphgen.grid(96), [0, 4000]),            # weights up to 1000: 10 bits
+        (_barbell(3000, 20000, 12, 5), [0]),       # small-frontier kernel in and out
+    ]
+
+
+def test_packed_sssp_matches_oracle():
+    """SSSP on packed arcs (one 32-bit word per arc) gives the oracle's
+    distances, bit for bit, on edge cases, tiles with ragged tails, the
+    small-frontier kernel and several weight widths."""
+    for g, srcs in _packed_cases():
+        dg = _dev(g)
+        arcs, wb = dg.ensure_packed()
+        assert wb == int(g.weights.max()).bit_length() if g.m else wb == 0
+        if g.m:
+            exp = (g.cols.astype(np.uint64) << wb) | g.weights.astype(np.uint64)
+            assert np.array_equal(arcs.cpu().numpy().view(np.uint32)[: g.m], exp.astype(np.uint32)), g.name
+        for s in srcs:
+            got = lbg.sssp(dg, int(s), packed=True).cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, O.dijkstra(g.offsets, g.cols, g.weights, int(s))), (g.name, s)
+    for gg, s in pins.tiny_graphs(count=20, seed=9):
+        got = lbg.sssp(_dev(gg), int(s), packed=True).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, O.dijkstra(gg.offsets, gg.cols, gg.weights, int(s)))
+
+
+def test_packed_range_errors():
+    # 2^23 node ids leave 9 bits: a weight of 1024 needs 11
+    n = 1 << 23
+    g = graphgen.from_edges(n, [0, 5], [n - 1, 3], [1024, 7], "wide")
+    dg = _dev(g)
+    with pytest.raises(lbg.LbgError, match="do not fit"):
+        dg.ensure_packed()
+    arcs = torch.zeros(2, dtype=torch.int32, device="cuda")
+    ws = lbg.Workspace("cuda")
+    buf = ws.get(lbg.workspace_bytes(n, 2, "balanced", True))
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    for wb in (32, -1, 10):
+        rc = lbg.lib.lbg_sssp_packed(lbg._ptr(dg.offsets), lbg._ptr(arcs), wb, n, 2, 0, lbg._ptr(out),
+                                     lbg._ptr(buf), buf.numel(), None, None)
+        assert rc == lbg.ERANGE, wb
+
+
 def _expected_slicing(g):
     S = lbg.slice_nodes(g.n)
     row = np.repeat(np.arange(g.n), g.degrees)
@@ -349,6 +404,15 @@ def test_device_argument_errors_leave_output_untouched():
 def rmat22():
     g = graphgen.rmat(22)
     return g, _dev(g), graphgen.sources(g, 64, graphgen.FAMILY_RMAT)
+
+
+def test_rmat22_full_packed(rmat22):
+    g, dg, srcs = rmat22
+    arcs, wb = dg.ensure_packed()
+    assert wb == 8
+    for s in srcs[:2]:
+        got = lbg.sssp(dg, int(s), packed=True).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, O.dijkstra(g.offsets, g.cols, g.weights, int(s)))
 
 
 @pytest.mark.parametrize("strat", FULL_STRATS)
