@@ -290,6 +290,25 @@ def run_strategies(lbg, torch, g, srcs, dev):
             res[f"{kind}_gteps"] = round(arcs / sum(ts) / 1e9, 3)
         out[strat] = res
         log(f"strategy {strat}: {res}")
+    # balanced SSSP on packed 32-bit arcs (one load per arc), when ids and
+    # weights fit in 32 bits
+    try:
+        dg.ensure_packed()
+    except lbg.LbgError:
+        return out
+    ts, arcs = [], 0
+    for s in srcs[:2]:
+        lv = lbg.bfs(dg, int(s), strategy="balanced", workspace=ws).cpu().numpy()
+        arcs += int(deg[lv != lbg.BFS_INF].sum())
+        lbg.sssp(dg, int(s), workspace=ws, packed=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lbg.sssp(dg, int(s), workspace=ws, packed=True)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    out["balanced_packed"] = {"wbits": dg.packed[1], "sssp_ms": [round(x * 1e3, 3) for x in ts],
+                              "sssp_gteps": round(arcs / sum(ts) / 1e9, 3)}
+    log(f"strategy balanced_packed: {out['balanced_packed']}")
     return out
 
 
