@@ -456,3 +456,42 @@ def test_workspace_reuse_across_sources(strat):
         assert np.array_equal(lv, O.bfs(g.offsets, g.cols, s)), f"bfs src={s}"
         d = lbg.sssp(dg, s, strategy=strat, workspace=ws).cpu().numpy().view(np.uint32)
         assert np.array_equal(d, O.dijkstra(g.offsets, g.cols, g.weights, s)), f"sssp src={s}"
+
+
+def test_concurrent_solves_on_two_streams():
+    """The header's thread-safety contract: solves running at the same time
+    from two host threads, each with its own stream, workspace and output,
+    give the oracle's answers (the library keeps per-thread control blocks
+    and events; the interpreter lock is released during the C calls)."""
+    import threading
+
+    g = graphgen.rmat(16)
+    dg = _dev(g)
+    srcs = [int(s) for s in graphgen.sources(g, 6, graphgen.FAMILY_RMAT)]
+    exp = {s: (O.bfs(g.offsets, g.cols, s), O.dijkstra(g.offsets, g.cols, g.weights, s)) for s in srcs}
+    errors = []
+
+    def worker(my_srcs, strat):
+        try:
+            stream = torch.cuda.Stream()
+            ws = lbg.Workspace("cuda")
+            for _ in range(3):
+                for s in my_srcs:
+                    lv = lbg.bfs(dg, s, strategy=strat, workspace=ws, stream=stream)
+                    d = lbg.sssp(dg, s, strategy=strat, workspace=ws, stream=stream)
+                    stream.synchronize()
+                    if not np.array_equal(lv.cpu().numpy(), exp[s][0]):
+                        errors.append(("bfs", strat, s))
+                    if not np.array_equal(d.cpu().numpy().view(np.uint32), exp[s][1]):
+                        errors.append(("sssp", strat, s))
+        except Exception as exc:  # surfaced below
+            errors.append(repr(exc))
+
+    ts = [threading.Thread(target=worker, args=(srcs[:3], "balanced")),
+          threading.Thread(target=worker, args=(srcs[3:], "binned"))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(120)
+    assert not any(t.is_alive() for t in ts)
+    assert not errors, errors
