@@ -219,6 +219,11 @@ struct PinnedCtl {
   }
 };
 thread_local PinnedCtl g_pinned;
+// Level count of this thread's previous single solve, per kind (BFS, SSSP),
+// or 0 when it used the small-frontier kernel: repeated solves on one graph
+// enqueue that many levels in the first batch, so a typical solve needs one
+// read-back and few empty launches.
+thread_local uint32_t g_level_hint[2] = {0u, 0u};
 thread_local std::vector<hipEvent_t> g_events;
 thread_local std::vector<int64_t> g_event_level;  // per event pair: level, or -1 = small-frontier launch
 
@@ -476,8 +481,9 @@ int solve(const Problem& P) {
   // then resumes from ctl->levels, the next level to expand.
   const bool small_ok = strat == LBG_BALANCED && (packed ? GR.small_p[nw] : GR.small[sv][nw]);
   uint32_t L = 0, L_prev = 0;
-  uint32_t batch = 8;
-  bool small = false;
+  const uint32_t hint = g_level_hint[P.is_sssp ? 1 : 0];
+  uint32_t batch = hint ? std::min<uint32_t>(std::max<uint32_t>(hint + 1, 8), 64) : 8;
+  bool small = false, used_small = false;
   size_t nev = 0;
   g_event_level.clear();
   const uint64_t level_cap = static_cast<uint64_t>(P.n) + 2;
@@ -541,9 +547,11 @@ int solve(const Problem& P) {
     small = small_ok && ef <= lbg::kSmallE && nfr <= lbg::kSmallF &&
             !(was_small && L == L_prev);  // a small step always advances; never spin
     if (was_small && !small) batch = 8;
+    used_small = used_small || small;
     L_prev = L;
   }
 
+  g_level_hint[P.is_sssp ? 1 : 0] = used_small ? 0u : host->levels;
   const int64_t p_upd = xsum(host, 2), p_atom = xsum(host, 3);
   if (profiling) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
