@@ -92,7 +92,7 @@ def recorded_traffic():
 
     h = hashlib.sha256()
     for f in ("paper_1711_00231_amd/csrc/lbg_kernels.hpp", "paper_1711_00231_amd/csrc/lbg_device.hpp",
-              "paper_1711_00231_amd/csrc/lbg_sliced.hpp"):
+              "paper_1711_00231_amd/csrc/lbg_sliced.hpp", "paper_1711_00231_amd/csrc/lbg.hip"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     out = {}
