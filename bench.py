@@ -507,8 +507,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(queries are independent; DESIGN.md describes how it would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (queries are "
+              "independent, so several GPUs would each take a share of the sources).", file=sys.stderr)
         sys.exit(2)
 
     import torch
