@@ -134,3 +134,28 @@ def test_graph_launched_batch_replays():
     for q, e in zip(queries[::-1], expect[::-1]):
         assert np.array_equal(got2[off: off + q[2] - q[1]], e), q
         off += q[2] - q[1]
+
+
+def test_full_size_batch_sampled_against_oracle():
+    """The batched benchmark configuration at full size (256 instances, 4
+    sources each, BFS and SSSP: 2,048 queries in one lbg_batch_solve call):
+    16 queries spread over the instances, the largest included, are checked
+    against the oracle on their own instance, bit for bit."""
+    gs = graphgen.batch_instances(256, hi_exp=18)
+    u, nb, eb = graphgen.pack(gs)
+    dg = lbg.DeviceGraph.from_numpy(u.offsets, u.cols, u.weights)
+    queries, owner = [], []
+    for i, g in enumerate(gs):
+        for s in graphgen.sources(g, 4, graphgen.FAMILY_BATCH, salt=i):
+            for kind in (lbg.KIND_BFS, lbg.KIND_SSSP):
+                queries.append((int(nb[i] + s), int(nb[i]), int(nb[i + 1]), kind))
+                owner.append((i, int(s), kind))
+    assert len(queries) == 2048
+    out = lbg.batch_solve(dg, queries)
+    starts = np.concatenate([[0], np.cumsum([q[2] - q[1] for q in queries])])
+    biggest = max(range(len(gs)), key=lambda i: gs[i].m)
+    pick = sorted(set(list(range(0, 2048, 137)) + [8 * biggest, 8 * biggest + 1]))
+    for k in pick:
+        i, s, kind = owner[k]
+        row = out[int(starts[k]): int(starts[k + 1])].cpu().numpy()
+        assert np.array_equal(row, _expected(gs[i], s, kind)), f"query {k} (instance {i}, src {s}, kind {kind})"
