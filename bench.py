@@ -264,16 +264,19 @@ def run_plain(args, lbg, torch, dev):
 # ----------------------------------------------------------- strategies --
 def run_strategies(lbg, torch, g, srcs, dev):
     """Node-based vs edge-based vs hierarchical vs balanced vs degree-binned
-    vs destination-sliced assignment on the same graph: BFS and SSSP from two
-    sources each (binned with bins autotuned on two other sources; the
-    sliced graph and the COO array are built before timing)."""
+    vs destination-sliced vs node splitting with child nodes on the same
+    graph: BFS and SSSP from two sources each (binned with bins autotuned on
+    two other sources; the sliced graph, the split graph (split size by the
+    histogram rule) and the COO array are built before timing)."""
     dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev, with_coo=True,
                                     with_slices=True)
+    sp = dg.ensure_split()
     deg = g.degrees
     tuned = lbg.autotune_bins(dg, [int(x) for x in srcs[2:4]])
     ws = lbg.Workspace(dev)
-    out = {"bins": tuned, "slice_min": lbg.get_slice_min()}
-    for strat in ("node", "edge", "hier", "balanced", "binned", "sliced"):
+    out = {"bins": tuned, "slice_min": lbg.get_slice_min(),
+           "split_graph": {"mdt": sp.mdt, "children": sp.children}}
+    for strat in ("node", "edge", "hier", "balanced", "binned", "sliced", "split"):
         res = {}
         for kind, f in (("bfs", lbg.bfs), ("sssp", lbg.sssp)):
             ts, arcs = [], 0

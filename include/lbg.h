@@ -45,6 +45,13 @@
  *                 their random node-state accesses stay within that XCD's L2;
  *                 smaller nodes are tiled together by all workgroups
  *                 (lbg_bfs_sliced, lbg_sssp_sliced)
+ *   LBG_SPLIT     node splitting with child nodes (Section III-B): a node
+ *                 with more than MDT out-arcs is cut into ceil(deg / MDT)
+ *                 pieces; it keeps the first, and child nodes of a split
+ *                 graph built once (lbg_split_graph) hold the others; a pushed node queues
+ *                 its own piece and its children's, which carry its distance
+ *                 (the parent-to-child propagation), and the pieces are tiled
+ *                 as in LBG_BALANCED (lbg_bfs_split, lbg_sssp_split)
  *   LBG_AUTO      currently LBG_BALANCED
  *
  * Conventions for every entry point
@@ -97,14 +104,17 @@ typedef enum {
   LBG_BINNED = 4,
   LBG_EDGE_NOCHUNK = 5,
   LBG_HIER = 6,
-  LBG_SLICED = 7
+  LBG_SLICED = 7,
+  LBG_SPLIT = 8
 } lbg_strategy;
 
 /* Counters of one solve (host struct, filled when `stats` is not NULL).
- * levels: number of non-empty frontiers (BFS: eccentricity of src + 1;
+ * levels: number of frontiers holding at least one out-arc (BFS: 1 + the
+ *         largest level of a reached node with out-arcs, which is the
+ *         eccentricity of src + 1 unless every farthest node is a sink;
  *         SSSP: Bellman-Ford iterations).
  * frontier_entries: total worklist entries processed (nodes; LBG_EDGE: edges;
- *         LBG_SLICED: (node, slice) pairs).
+ *         LBG_SLICED: (node, slice) pairs; LBG_SPLIT: pieces).
  * edges_scanned: total arcs relaxed (BFS: the arcs leaving reached nodes;
  *         SSSP: at least that, re-relaxations included).
  * updates: successful distance improvements (SSSP) or discoveries (BFS).
@@ -215,6 +225,58 @@ int lbg_bfs_sliced(const int32_t* offsets, const int32_t* slice_offsets, const i
 int lbg_sssp_sliced(const int32_t* offsets, const int32_t* slice_offsets, const int32_t* cols,
                     const uint32_t* weights, int32_t n, int64_t m, int32_t src, uint32_t* dist_out,
                     void* workspace, size_t workspace_bytes, lbg_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Split graphs (LBG_SPLIT; node splitting with child nodes, Section III-B).
+ *
+ * Under split size mdt (>= 1; 0 = no splitting) a node v with d > mdt
+ * out-arcs has p = ceil(d / mdt) pieces, the first d % p of them one arc
+ * longer (piece k starts at arc k * floor(d / p) + min(k, d % p)); v keeps
+ * piece 0 and pieces 1 .. p - 1 go to p - 1 child nodes.  The split graph
+ * has n + C nodes (C = total child count): node v < n holds v's piece 0,
+ * node n + child_base[v] + k - 1 holds v's piece k.  Arcs still point at
+ * original nodes only.  The histogram rule of Section III-B for mdt is
+ * lbg_degree_mdt.
+ *
+ * lbg_split_scratch_bytes(n): device scratch the next two calls need
+ * (12 bytes per 4096 nodes, rounded up to 256).
+ * lbg_split_count: *children_out = C.  Returns after a read-back.
+ * lbg_split_graph: writes
+ *   split_offsets[n + C + 1] int32: CSR offsets of the split graph; the
+ *     parents' pieces come first in the arc array (in node order), then the
+ *     children's (in child order), so split_offsets[n] is the number of arcs
+ *     in parents' pieces and split_offsets[n + C] = m;
+ *   child_base[n + 1] int32: exclusive prefix sum of the child counts;
+ *   cols_out[m], weights_out[m]: the arcs regrouped in that order.
+ * children must equal lbg_split_count's result (LBG_EINVAL otherwise).
+ * weights and weights_out are both NULL (BFS only) or both given (m > 0).
+ * Outputs are device buffers the caller allocates, not overlapping the
+ * inputs; offsets outside [0, m] are clamped (lbg_validate_csr first on
+ * untrusted input).  LBG_ERANGE if n + C does not fit in int32.
+ *
+ * lbg_bfs_split / lbg_sssp_split: as lbg_bfs / lbg_sssp on the split graph:
+ * split_offsets, child_base, cols = cols_out, weights = weights_out, the
+ * original n, the child count C; workspace of at least
+ * lbg_split_workspace_bytes(n, m, C, is_sssp) bytes (two worklists of n + C
+ * entries and their tile marks; lbg_workspace_bytes(n, m, LBG_SPLIT, .)
+ * gives the bound for C = m).  levels_out / dist_out have n entries; results
+ * are identical to every other strategy's.  lbg_bfs / lbg_sssp reject
+ * LBG_SPLIT with LBG_EINVAL. */
+size_t lbg_split_scratch_bytes(int32_t n);
+int lbg_split_count(const int32_t* offsets, int32_t n, int64_t m, int32_t mdt, int64_t* children_out,
+                    void* scratch, size_t scratch_bytes, void* stream);
+int lbg_split_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, int32_t mdt, int64_t children, int32_t* split_offsets, int32_t* child_base,
+                    int32_t* cols_out, uint32_t* weights_out, void* scratch, size_t scratch_bytes,
+                    void* stream);
+size_t lbg_split_workspace_bytes(int32_t n, int64_t m, int64_t children, int32_t is_sssp);
+int lbg_bfs_split(const int32_t* split_offsets, const int32_t* child_base, const int32_t* cols, int32_t n,
+                  int64_t children, int64_t m, int32_t src, int32_t* levels_out, void* workspace,
+                  size_t workspace_bytes, lbg_stats* stats, void* stream);
+int lbg_sssp_split(const int32_t* split_offsets, const int32_t* child_base, const int32_t* cols,
+                   const uint32_t* weights, int32_t n, int64_t children, int64_t m, int32_t src,
+                   uint32_t* dist_out, void* workspace, size_t workspace_bytes, lbg_stats* stats,
+                   void* stream);
 
 /* Structural check of a CSR graph on the device: offsets[0] == 0,
  * non-decreasing offsets, offsets[n] == m, every col in [0, n).  Needs

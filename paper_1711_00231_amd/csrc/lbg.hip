@@ -13,6 +13,7 @@
 #include "../../include/lbg.h"
 #include "lbg_kernels.hpp"
 #include "lbg_sliced.hpp"
+#include "lbg_split.hpp"
 
 namespace {
 
@@ -40,7 +41,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_SLICED; }
+bool strategy_ok(int32_t s) { return s >= LBG_AUTO && s <= LBG_SPLIT; }
 bool edge_wl(int32_t s) { return s == LBG_EDGE || s == LBG_EDGE_NOCHUNK; }
 int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
@@ -50,7 +51,9 @@ struct Layout {
   uint32_t node_cap, tile_cap, edge_cap;
 };
 
-Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
+// children: child nodes of the split graph (LBG_SPLIT; negative: the bound
+// m, which holds for every split size).
+Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp, int64_t children = -1) {
   Layout L{};
   const int32_t s = resolve(strategy);
   size_t off = 0;
@@ -87,8 +90,12 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp) {
       L.tile[b] = take(sizeof(int32_t) * static_cast<size_t>(lbg::kLists) * L.tile_cap);
     }
   } else {
-    // split hubs add at most m / kMinMdt entries per level
-    L.node_cap = static_cast<uint32_t>(n + (s == LBG_BINNED ? m / lbg::kMinMdt + 1 : 0));
+    // split hubs add at most m / kMinMdt entries per level; a split graph at
+    // most one entry per child node
+    int64_t extra = 0;
+    if (s == LBG_BINNED) extra = m / lbg::kMinMdt + 1;
+    if (s == LBG_SPLIT) extra = children < 0 ? m : children;
+    L.node_cap = static_cast<uint32_t>(n + extra);
     L.tile_cap = static_cast<uint32_t>((m + lbg::kMinTile - 1) / lbg::kMinTile + 2);
     for (int b = 0; b < 2; ++b) {
       L.node[b] = take(sizeof(int32_t) * static_cast<size_t>(L.node_cap));
@@ -136,6 +143,7 @@ struct Grids {
   int bal[2][2], node[2], edge[2], edge_nc[2], multi[2], binned[2], hier[2];  // bal[is_sssp][narrow], multi[narrow]
   int sliced[2][2];                                      // [is_sssp][narrow], a multiple of 8 (>= 8)
   int bal_p[2];                                          // SSSP with packed arcs [narrow]
+  int bal_s[2][2];                                       // split graph [is_sssp][narrow]
   bool small_p[2];
   bool small[2][2];                                      // small-frontier kernel fits the device
 };
@@ -183,6 +191,10 @@ const Grids& grids() {
     g[dev].multi[1] = resident_grid(lbg::k_expand_balanced<true, true, true>);
     g[dev].bal_p[0] = resident_grid(lbg::k_expand_balanced<true, false, false, true>);
     g[dev].bal_p[1] = resident_grid(lbg::k_expand_balanced<true, true, false, true>);
+    g[dev].bal_s[0][0] = resident_grid(lbg::k_expand_balanced<false, false, false, false, true>);
+    g[dev].bal_s[0][1] = resident_grid(lbg::k_expand_balanced<false, true, false, false, true>);
+    g[dev].bal_s[1][0] = resident_grid(lbg::k_expand_balanced<true, false, false, false, true>);
+    g[dev].bal_s[1][1] = resident_grid(lbg::k_expand_balanced<true, true, false, false, true>);
     g[dev].small_p[0] = fits_lds(lbg::k_expand_small<true, false, true>);
     g[dev].small_p[1] = fits_lds(lbg::k_expand_small<true, true, true>);
     g[dev].sliced[0][0] = slice_grid(resident_grid(lbg::k_expand_sliced<false, false>));
@@ -287,6 +299,8 @@ struct Problem {
   const int32_t* soff = nullptr;  // their slice offsets
   const uint32_t* arcs = nullptr; // lbg_sssp_packed: packed arcs (cols/weights unused)
   int32_t wbits = 0;
+  const int32_t* child_base = nullptr;  // lbg_bfs_split / lbg_sssp_split: the split graph's
+  int64_t children = 0;                 // child table and child count
 };
 
 int check_common(const Problem& P) {
@@ -303,6 +317,11 @@ int check_common(const Problem& P) {
   if ((resolve(P.strategy) == LBG_SLICED) != P.sliced)
     return fail(LBG_EINVAL, "LBG_SLICED runs through lbg_bfs_sliced / lbg_sssp_sliced only");
   if (P.sliced && !P.soff) return fail(LBG_EINVAL, "null slice_offsets pointer");
+  if ((resolve(P.strategy) == LBG_SPLIT) != (P.child_base != nullptr))
+    return fail(LBG_EINVAL, "LBG_SPLIT runs through lbg_bfs_split / lbg_sssp_split only");
+  if (P.child_base && (P.children < 0 || P.children > P.m || P.n + P.children >= INT32_MAX))
+    return fail(LBG_ERANGE, "children must be in [0, m] with n + children < INT32_MAX (got %lld)",
+                static_cast<long long>(P.children));
   if (P.arcs) {
     if (P.wbits < 0 || P.wbits > 31)
       return fail(LBG_ERANGE, "wbits must be in [0, 31] (got %d)", P.wbits);
@@ -311,7 +330,7 @@ int check_common(const Problem& P) {
   }
   if (reinterpret_cast<uintptr_t>(P.ws) % kAlign)
     return fail(LBG_EINVAL, "workspace must be %zu-byte aligned", kAlign);
-  const size_t need = layout(P.n, P.m, P.strategy, P.is_sssp).total;
+  const size_t need = layout(P.n, P.m, P.strategy, P.is_sssp, P.children).total;
   if (P.ws_bytes < need)
     return fail(LBG_ENOMEM, "workspace has %zu bytes, needs %zu", P.ws_bytes, need);
   return LBG_OK;
@@ -321,7 +340,7 @@ int solve(const Problem& P) {
   int rc = check_common(P);
   if (rc) return rc;
   const int32_t strat = resolve(P.strategy);
-  const Layout Lay = layout(P.n, P.m, P.strategy, P.is_sssp);
+  const Layout Lay = layout(P.n, P.m, P.strategy, P.is_sssp, P.children);
   char* ws = static_cast<char*>(P.ws);
 
   KArgs a{};
@@ -360,6 +379,8 @@ int solve(const Problem& P) {
   a.tile_cap = Lay.tile_cap;
   a.edge_cap = Lay.edge_cap;
   const bool sl = strat == LBG_SLICED;
+  const bool split = strat == LBG_SPLIT;
+  a.child_base = P.child_base;
   if (sl) {
     a.soff = P.soff;
     a.sliced = 1u;
@@ -389,8 +410,9 @@ int solve(const Problem& P) {
   const Grids& GR = grids();
   const int sv = P.is_sssp ? 1 : 0;
   // 32-bit element offsets are enough when every array stays below 4 GiB
-  // (the slice offsets have 8n + 1 entries)
-  const bool narrow = P.n < (sl ? (1 << 26) : (1 << 29)) && P.m < (int64_t{1} << 30);
+  // (the slice offsets have 8n + 1 entries, the split offsets n + children + 1)
+  const bool narrow = (split ? P.n + P.children : P.n) < (sl ? (1 << 26) : (1 << 29)) &&
+                      P.m < (int64_t{1} << 30);
   const int nw = narrow ? 1 : 0;
   const int init_blocks = static_cast<int>(
       std::min<int64_t>(std::max<int64_t>((static_cast<int64_t>(P.n) + lbg::kBlock - 1) / lbg::kBlock, 1), 4096));
@@ -438,6 +460,10 @@ int solve(const Problem& P) {
           for (uint32_t k = 0; k < hier_subs; ++k)
             hipLaunchKernelGGL((lbg::k_expand_hier<true>), dim3(GR.hier[sv]), dim3(lbg::kBlock), 0, st, a, L, k, hier_mdt);
           break;
+        case LBG_SPLIT:
+          if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true, false, false, true>), dim3(GR.bal_s[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          else hipLaunchKernelGGL((lbg::k_expand_balanced<true, false, false, false, true>), dim3(GR.bal_s[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          break;
         default:
           if (packed) {
             if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<true, true, false, true>), dim3(GR.bal_p[nw]), dim3(lbg::kBlock), 0, st, a, L);
@@ -463,6 +489,10 @@ int solve(const Problem& P) {
           hipLaunchKernelGGL(lbg::k_hier_reset, dim3(1), dim3(64), 0, st, a.ctl);
           for (uint32_t k = 0; k < hier_subs; ++k)
             hipLaunchKernelGGL((lbg::k_expand_hier<false>), dim3(GR.hier[sv]), dim3(lbg::kBlock), 0, st, a, L, k, hier_mdt);
+          break;
+        case LBG_SPLIT:
+          if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<false, true, false, false, true>), dim3(GR.bal_s[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+          else hipLaunchKernelGGL((lbg::k_expand_balanced<false, false, false, false, true>), dim3(GR.bal_s[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
           break;
         default:
           if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<false, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
@@ -1278,6 +1308,113 @@ int lbg_sssp_sliced(const int32_t* offsets, const int32_t* slice_offsets, const 
                     void* workspace, size_t workspace_bytes, lbg_stats* stats, void* stream) {
   Problem P{offsets, cols, weights, nullptr, n, m, src, dist_out, workspace, workspace_bytes,
             LBG_SLICED, 1, stats, static_cast<hipStream_t>(stream), true, slice_offsets};
+  return solve(P);
+}
+
+size_t lbg_split_scratch_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  const size_t nb = (static_cast<size_t>(n) + lbg::kSplitChunk - 1) / lbg::kSplitChunk;
+  return align_up(sizeof(uint32_t) * 3 * (nb + 1));
+}
+
+namespace {
+
+// Per-workgroup sums and their scan (k_split_sums, k_split_scan); leaves the
+// three totals (children, own-piece arcs, children's arcs) in totals.
+int split_scan(const int32_t* offsets, int32_t n, int64_t m, int32_t mdt, void* scratch,
+               size_t scratch_bytes, hipStream_t st, uint32_t totals[3]) {
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX)
+    return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
+  if (mdt < 0) return fail(LBG_EINVAL, "mdt must be >= 0 (got %d)", mdt);
+  if (!offsets || !scratch) return fail(LBG_EINVAL, "null offsets/scratch pointer");
+  if (reinterpret_cast<uintptr_t>(scratch) % kAlign)
+    return fail(LBG_EINVAL, "scratch must be %zu-byte aligned", kAlign);
+  if (scratch_bytes < lbg_split_scratch_bytes(n))
+    return fail(LBG_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, lbg_split_scratch_bytes(n));
+  const uint32_t nb = static_cast<uint32_t>((static_cast<int64_t>(n) + lbg::kSplitChunk - 1) / lbg::kSplitChunk);
+  uint32_t* sums = static_cast<uint32_t*>(scratch);
+  hipLaunchKernelGGL(lbg::k_split_sums, dim3(nb), dim3(lbg::kBlock), 0, st, offsets, static_cast<uint32_t>(n),
+                     static_cast<uint32_t>(m), static_cast<uint32_t>(mdt), sums);
+  hipLaunchKernelGGL(lbg::k_split_scan, dim3(1), dim3(lbg::kBlock), 0, st, sums, nb);
+  HIP_TRY(hipGetLastError());
+  Ctl* host = pinned_ctl();
+  if (!host) return fail(LBG_EHIP, "hipHostMalloc of the readback word failed");
+  HIP_TRY(hipMemcpyAsync(host, sums + 3 * static_cast<size_t>(nb), 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::memcpy(totals, host, 3 * sizeof(uint32_t));
+  return LBG_OK;
+}
+
+}  // namespace
+
+int lbg_split_count(const int32_t* offsets, int32_t n, int64_t m, int32_t mdt, int64_t* children_out,
+                    void* scratch, size_t scratch_bytes, void* stream) {
+  if (!children_out) return fail(LBG_EINVAL, "null children_out pointer");
+  uint32_t tot[3];
+  const int rc = split_scan(offsets, n, m, mdt, scratch, scratch_bytes, static_cast<hipStream_t>(stream), tot);
+  if (rc) return rc;
+  *children_out = tot[0];
+  return LBG_OK;
+}
+
+int lbg_split_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, int32_t mdt, int64_t children, int32_t* split_offsets, int32_t* child_base,
+                    int32_t* cols_out, uint32_t* weights_out, void* scratch, size_t scratch_bytes,
+                    void* stream) {
+  if (!split_offsets || !child_base || (m > 0 && (!cols || !cols_out)))
+    return fail(LBG_EINVAL, "null split_offsets/child_base/cols/cols_out pointer");
+  if (m > 0 && (weights == nullptr) != (weights_out == nullptr))
+    return fail(LBG_EINVAL, "weights and weights_out must both be given or both be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t tot[3];
+  int rc = split_scan(offsets, n, m, mdt, scratch, scratch_bytes, st, tot);
+  if (rc) return rc;
+  if (static_cast<int64_t>(tot[0]) != children)
+    return fail(LBG_EINVAL, "children = %lld, but mdt = %d gives %u child nodes",
+                static_cast<long long>(children), mdt, tot[0]);
+  if (static_cast<int64_t>(n) + children >= INT32_MAX)
+    return fail(LBG_ERANGE, "n + children = %lld does not fit in int32", static_cast<long long>(n + children));
+  const uint32_t nb = static_cast<uint32_t>((static_cast<int64_t>(n) + lbg::kSplitChunk - 1) / lbg::kSplitChunk);
+  hipLaunchKernelGGL(lbg::k_split_build, dim3(nb), dim3(lbg::kBlock), 0, st, offsets, static_cast<uint32_t>(n),
+                     static_cast<uint32_t>(m), static_cast<uint32_t>(mdt), static_cast<const uint32_t*>(scratch), nb,
+                     split_offsets, child_base);
+  if (m > 0) {
+    const int blocks = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(n) + lbg::kWaves - 1) / lbg::kWaves, 16384));
+    hipLaunchKernelGGL(lbg::k_split_copy, dim3(blocks), dim3(lbg::kBlock), 0, st, offsets, cols, weights,
+                       static_cast<uint32_t>(n), static_cast<uint32_t>(m), split_offsets, child_base, cols_out,
+                       weights_out);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return LBG_OK;
+}
+
+size_t lbg_split_workspace_bytes(int32_t n, int64_t m, int64_t children, int32_t is_sssp) {
+  if (n <= 0 || m < 0 || m > INT32_MAX || children < 0 || children > m) return 0;
+  return layout(n, m, LBG_SPLIT, is_sssp ? 1 : 0, children).total;
+}
+
+int lbg_bfs_split(const int32_t* split_offsets, const int32_t* child_base, const int32_t* cols, int32_t n,
+                  int64_t children, int64_t m, int32_t src, int32_t* levels_out, void* workspace,
+                  size_t workspace_bytes, lbg_stats* stats, void* stream) {
+  if (!child_base) return fail(LBG_EINVAL, "null child_base pointer");
+  Problem P{split_offsets, cols, nullptr, nullptr, n, m, src, levels_out, workspace, workspace_bytes,
+            LBG_SPLIT, 0, stats, static_cast<hipStream_t>(stream)};
+  P.child_base = child_base;
+  P.children = children;
+  return solve(P);
+}
+
+int lbg_sssp_split(const int32_t* split_offsets, const int32_t* child_base, const int32_t* cols,
+                   const uint32_t* weights, int32_t n, int64_t children, int64_t m, int32_t src,
+                   uint32_t* dist_out, void* workspace, size_t workspace_bytes, lbg_stats* stats,
+                   void* stream) {
+  if (!child_base) return fail(LBG_EINVAL, "null child_base pointer");
+  Problem P{split_offsets, cols, weights, nullptr, n, m, src, dist_out, workspace, workspace_bytes,
+            LBG_SPLIT, 1, stats, static_cast<hipStream_t>(stream)};
+  P.child_base = child_base;
+  P.children = children;
   return solve(P);
 }
 

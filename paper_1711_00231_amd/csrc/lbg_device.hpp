@@ -130,6 +130,11 @@ struct KArgs {
   uint32_t scap, stcap;
   uint32_t slice_nodes;
   uint32_t slice_min;
+  // Split graph (node splitting with child nodes): offsets covers n parents
+  // then the children; the children of parent v are nodes
+  // n + child_base[v] .. n + child_base[v + 1] - 1, each holding one piece
+  // of v's arcs (null: no split graph).
+  const int32_t* child_base;
 };
 
 // Pieces of a node with d out-arcs under split size mdt, and piece k's
@@ -413,34 +418,71 @@ __device__ __forceinline__ void write_entry(const KArgs& a, const Frontier& out,
   }
 }
 
+// Split graph: the children of parent v and the arcs they hold in total.
+__device__ __forceinline__ void split_children(const KArgs& a, int32_t v, int32_t* cb, int32_t* ce,
+                                               int32_t* arcs) {
+  *cb = a.child_base[v];
+  *ce = a.child_base[v + 1];
+  *arcs = *ce > *cb ? a.offsets[a.n + *ce] - a.offsets[a.n + *cb] : 0;
+}
+
+// Split graph: entries i, i + 1, ... for parent v's own piece (first arc s,
+// d arcs; skipped when empty) and then each of its children's pieces, edge
+// prefixes from p on.  Every piece carries the parent's id, so a child is
+// relaxed with its parent's distance (the parent-to-child propagation).
+template <int kPay, uint32_t kTileE, bool kNarrow>
+__device__ __forceinline__ void write_split_entries(const KArgs& a, const Frontier& out, uint32_t i,
+                                                    uint32_t p, int32_t v, int32_t q, int32_t s,
+                                                    int32_t d, int32_t cb, int32_t ce) {
+  if (d > 0) {
+    write_entry<kPay, kTileE, kNarrow>(a, out, i, p, v, q, s, d);
+    ++i;
+    p += static_cast<uint32_t>(d);
+  }
+  for (int32_t c = cb; c < ce; ++c) {
+    const int32_t cs = a.offsets[a.n + c];
+    const int32_t cl = a.offsets[a.n + c + 1] - cs;
+    if (cl <= 0) continue;
+    write_entry<kPay, kTileE, kNarrow>(a, out, i, p, v, q, cs, cl);
+    ++i;
+    p += static_cast<uint32_t>(cl);
+  }
+}
+
 // Wave-direct append of the lanes with `act` set (convergent); used when a
 // wave queue cannot take a whole push, and to seed batched worklists.
-template <int kPay, uint32_t kTileE, bool kNarrow>
+template <int kPay, uint32_t kTileE, bool kNarrow, bool kSplit = false>
 __device__ __forceinline__ void wave_append(const KArgs& a, bool act, int32_t v, int32_t q,
                                             const Frontier& out, int ctr_idx) {
-  int32_t s = 0, d = 0;
+  int32_t s = 0, d = 0, cb = 0, ce = 0, ca = 0;
   if (act) {
     s = *at<kNarrow>(a.offsets, v);
     d = *at<kNarrow>(a.offsets, v + 1) - s;
+    if (kSplit) split_children(a, v, &cb, &ce, &ca);
   }
-  const bool ok = act && d > 0;
+  const bool ok = act && (d > 0 || ca > 0);
   const uint64_t mask = __ballot(ok);
   if (mask == 0) return;
-  const uint32_t dd = ok ? static_cast<uint32_t>(d) : 0u;
+  const uint32_t dd = ok ? static_cast<uint32_t>(d + ca) : 0u;
+  const uint32_t nn = ok ? static_cast<uint32_t>((d > 0 ? 1 : 0) + (ce - cb)) : 0u;
   const uint32_t inc = wave_incl_scan(dd);
   const uint32_t tot = __shfl(inc, 63, 64);
+  const uint32_t inn = kSplit ? wave_incl_scan(nn) : lane_rank(mask) + 1u;
+  const uint32_t totn = kSplit ? __shfl(inn, 63, 64) : static_cast<uint32_t>(__popcll(mask));
   unsigned long long base = 0;
   if (lane_id() == 0)
-    base = atomicAdd(&a.ctl->ctr[ctr_idx],
-                     (static_cast<unsigned long long>(__popcll(mask)) << 32) | tot);
+    base = atomicAdd(&a.ctl->ctr[ctr_idx], (static_cast<unsigned long long>(totn) << 32) | tot);
   base = bcast64(base, 0);
-  if (ok)
-    write_entry<kPay, kTileE, kNarrow>(a, out, static_cast<uint32_t>(base >> 32) + lane_rank(mask),
-                                       static_cast<uint32_t>(base) + inc - dd, v, q, s, d);
+  if (ok) {
+    const uint32_t i = static_cast<uint32_t>(base >> 32) + (kSplit ? inn - nn : lane_rank(mask));
+    const uint32_t p = static_cast<uint32_t>(base) + inc - dd;
+    if (kSplit) write_split_entries<kPay, kTileE, kNarrow>(a, out, i, p, v, q, s, d, cb, ce);
+    else write_entry<kPay, kTileE, kNarrow>(a, out, i, p, v, q, s, d);
+  }
 }
 
 // Queue (v, q) if `want` (convergent per wave).  `count` is wave-uniform.
-template <int kPay, uint32_t kTileE, bool kNarrow>
+template <int kPay, uint32_t kTileE, bool kNarrow, bool kSplit = false>
 __device__ __forceinline__ void wq_push(const KArgs& a, int32_t* qv, int32_t* qq, uint32_t& count,
                                         bool want, int32_t v, int32_t q, const Frontier& out,
                                         int ctr_idx) {
@@ -455,15 +497,24 @@ __device__ __forceinline__ void wq_push(const KArgs& a, int32_t* qv, int32_t* qq
   const uint32_t c = static_cast<uint32_t>(__popcll(mask));
   count = min(count + c, static_cast<uint32_t>(kWQ));
   const bool over = want && !fits;
-  if (__ballot(over)) wave_append<kPay, kTileE, kNarrow>(a, over, v, q, out, ctr_idx);
+  if (__ballot(over)) wave_append<kPay, kTileE, kNarrow, kSplit>(a, over, v, q, out, ctr_idx);
   __builtin_amdgcn_wave_barrier();
 }
+
+// Split graph: each queued parent's child range and the arcs its children
+// hold (empty without a split graph, so the plain flush keeps its layout).
+template <bool kOn, int R>
+struct SplitKids {
+  int32_t cb[R], ce[R], ca[R];
+};
+template <int R>
+struct SplitKids<false, R> {};
 
 // A wave queue's flush, split so a workgroup can merge the reservations of
 // its four queues: prepare() reads degrees and scans within the wave,
 // write() stores the entries once the base of the reservation is known.
-template <int kPay, uint32_t kTileE, bool kNarrow>
-struct WaveFlush {
+template <int kPay, uint32_t kTileE, bool kNarrow, bool kSplit = false>
+struct WaveFlush : SplitKids<kSplit, kWQ / 64> {
   static constexpr int R = kWQ / 64;
   int32_t vs[R], ss[R], ds[R], qs[kPay == 2 ? R : 1];
   uint32_t pn[R], pe[R];
@@ -491,12 +542,25 @@ struct WaveFlush {
         ds[r] = *at<kNarrow>(a.offsets, vs[r] + 1);
       }
     }
+    if constexpr (kSplit) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        this->cb[r] = 0;
+        this->ce[r] = 0;
+        this->ca[r] = 0;
+        if (r * 64 + lane < count) split_children(a, vs[r], &this->cb[r], &this->ce[r], &this->ca[r]);
+      }
+    }
     uint32_t cn = 0, ce = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       ds[r] -= ss[r];
-      const uint32_t n1 = ds[r] > 0 ? 1u : 0u;
-      const uint32_t e1 = ds[r] > 0 ? static_cast<uint32_t>(ds[r]) : 0u;
+      uint32_t n1 = ds[r] > 0 ? 1u : 0u;
+      uint32_t e1 = ds[r] > 0 ? static_cast<uint32_t>(ds[r]) : 0u;
+      if constexpr (kSplit) {
+        n1 += static_cast<uint32_t>(this->ce[r] - this->cb[r]);
+        e1 += static_cast<uint32_t>(this->ca[r]);
+      }
       const uint32_t in = wave_incl_scan(n1), ie = wave_incl_scan(e1);
       pn[r] = cn + in - n1;
       pe[r] = ce + ie - e1;
@@ -510,10 +574,18 @@ struct WaveFlush {
   __device__ __forceinline__ void write(const KArgs& a, const Frontier& out, uint32_t nb,
                                         uint32_t eb) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (ds[r] > 0)
-        write_entry<kPay, kTileE, kNarrow>(a, out, nb + pn[r], eb + pe[r], vs[r],
-                                           kPay == 2 ? qs[kPay == 2 ? r : 0] : 0, ss[r], ds[r]);
+    for (int r = 0; r < R; ++r) {
+      if constexpr (kSplit) {
+        if (ds[r] > 0 || this->ce[r] > this->cb[r])
+          write_split_entries<kPay, kTileE, kNarrow>(a, out, nb + pn[r], eb + pe[r], vs[r],
+                                                     kPay == 2 ? qs[kPay == 2 ? r : 0] : 0, ss[r], ds[r],
+                                                     this->cb[r], this->ce[r]);
+      } else {
+        if (ds[r] > 0)
+          write_entry<kPay, kTileE, kNarrow>(a, out, nb + pn[r], eb + pe[r], vs[r],
+                                             kPay == 2 ? qs[kPay == 2 ? r : 0] : 0, ss[r], ds[r]);
+      }
+    }
   }
 
   // Standalone flush by one wavefront.

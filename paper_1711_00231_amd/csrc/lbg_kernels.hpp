@@ -221,6 +221,59 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
     const uint32_t tiles = (static_cast<uint32_t>(d0) + T - 1) / T;
     for (uint32_t t = gid; t < tiles; t += stride) a.fr[0].tile_node[t] = 0;
   }
+  if (!kEdgeWl && a.child_base) {
+    // split graph: the source's own piece, then its children's pieces (one
+    // thread; tile marks by the thread that owns each tile)
+    const int32_t cb = a.child_base[src], ce = a.child_base[src + 1];
+    if (gid == 0) {
+      uint32_t i = 0, p = 0;
+      if (d0 > 0) {
+        a.fr[0].node[0] = src;
+        a.fr[0].eprefix[0] = 0u;
+        a.fr[0].estart[0] = s0;
+        i = 1;
+        p = static_cast<uint32_t>(d0);
+      }
+      for (int32_t c = cb; c < ce && i < a.node_cap; ++c) {
+        const int32_t cs = a.offsets[a.n + c], cl = a.offsets[a.n + c + 1] - cs;
+        if (cl <= 0) continue;
+        a.fr[0].node[i] = src;
+        a.fr[0].eprefix[i] = p;
+        a.fr[0].estart[i] = cs;
+        ++i;
+        p += static_cast<uint32_t>(cl);
+      }
+      a.ctl->ctr[0] = p > 0 ? ((static_cast<unsigned long long>(i) << 32) | p) : 0ull;
+      a.ctl->ctr[1] = 0ull;
+      a.ctl->ctr[2] = 0ull;
+    }
+    // tile t starts in the piece holding edge t * T
+    constexpr uint32_t T = TileCfg<kSssp>::kEdges;
+    const int32_t tot = d0 + (ce > cb ? a.offsets[a.n + ce] - a.offsets[a.n + cb] : 0);
+    const uint32_t tiles = tot > 0 ? (static_cast<uint32_t>(tot) + T - 1) / T : 0u;
+    for (uint32_t t = gid; t < tiles && t < a.tile_cap; t += stride) {
+      const uint32_t e = t * T;
+      uint32_t i = 0, p = 0;
+      if (d0 > 0) {
+        if (e < static_cast<uint32_t>(d0)) {
+          a.fr[0].tile_node[t] = 0;
+          continue;
+        }
+        i = 1;
+        p = static_cast<uint32_t>(d0);
+      }
+      for (int32_t c = cb; c < ce; ++c) {
+        const int32_t cl = a.offsets[a.n + c + 1] - a.offsets[a.n + c];
+        if (cl <= 0) continue;
+        if (e < p + static_cast<uint32_t>(cl)) break;
+        ++i;
+        p += static_cast<uint32_t>(cl);
+      }
+      a.fr[0].tile_node[t] = static_cast<int32_t>(i);
+    }
+    if (gid < kXcds * 16) a.ctl->xstat[gid / 16][gid % 16] = 0ull;
+    return;
+  }
   // the source's entry (pieces of at most a.mdt arcs for the binned strategy)
   const uint32_t pc = kEdgeWl ? 0u : split_count(static_cast<uint32_t>(d0 > 0 ? d0 : 0), a.mdt);
   for (uint32_t k = gid; k < pc; k += stride) {
@@ -313,7 +366,7 @@ __device__ __forceinline__ bool level_fits(const KArgs& a, unsigned long long c)
 // One level of the balanced expansion by the whole grid (all threads of
 // every block must call it).  c = the level's packed tail, non-empty and
 // within capacity.
-template <bool kSssp, bool kNarrow, bool kMulti, bool kPacked = false>
+template <bool kSssp, bool kNarrow, bool kMulti, bool kPacked = false, bool kSplit = false>
 __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigned long long c) {
   static_assert(!kMulti || kSssp, "batched solves use the SSSP relaxation");
   static_assert(!kPacked || (kSssp && !kMulti), "packed arcs: single SSSP solves");
@@ -568,10 +621,10 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
     if (__any(bad) && lane == 0) atomicOr(&a.ctl->error, kErrBadArc);
 #pragma unroll
     for (int r = 0; r < kItems; ++r)
-      wq_push<kPay, T, kNarrow>(a, w.qv, w.qq, qcount, push[r], vv[r], kMulti ? qd[kMulti ? r : 0] : 0,
-                                nxt, nctr);
+      wq_push<kPay, T, kNarrow, kSplit>(a, w.qv, w.qq, qcount, push[r], vv[r], kMulti ? qd[kMulti ? r : 0] : 0,
+                                        nxt, nctr);
     if (qcount >= kWQ / 2) {
-      WaveFlush<kPay, T, kNarrow> f;
+      WaveFlush<kPay, T, kNarrow, kSplit> f;
       f.flush(a, w.qv, w.qq, qcount, nxt, nctr);
       qcount = 0;
     }
@@ -579,7 +632,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   }
 
   // Final flush: one reservation for the whole workgroup.
-  WaveFlush<kPay, T, kNarrow> f;
+  WaveFlush<kPay, T, kNarrow, kSplit> f;
   f.prepare(a, w.qv, w.qq, qcount);
   if (lane == 0) {
     merge[wid] = f.tot_n;
@@ -603,7 +656,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   add_stats(a, upd, atom);
 }
 
-template <bool kSssp, bool kNarrow, bool kMulti, bool kPacked = false>
+template <bool kSssp, bool kNarrow, bool kMulti, bool kPacked = false, bool kSplit = false>
 __device__ __forceinline__ void balanced_level(const KArgs& a, uint32_t L) {
   const unsigned long long c = level_begin(a, L);
   if (static_cast<uint32_t>(c) == 0u) return;
@@ -611,12 +664,12 @@ __device__ __forceinline__ void balanced_level(const KArgs& a, uint32_t L) {
     if (threadIdx.x == 0) atomicOr(&a.ctl->error, kErrNodeCap);
     return;
   }
-  expand_level<kSssp, kNarrow, kMulti, kPacked>(a, L, c);
+  expand_level<kSssp, kNarrow, kMulti, kPacked, kSplit>(a, L, c);
 }
 
-template <bool kSssp, bool kNarrow, bool kMulti = false, bool kPacked = false>
+template <bool kSssp, bool kNarrow, bool kMulti = false, bool kPacked = false, bool kSplit = false>
 __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
-  balanced_level<kSssp, kNarrow, kMulti, kPacked>(a, L);
+  balanced_level<kSssp, kNarrow, kMulti, kPacked, kSplit>(a, L);
 }
 
 // Graph-launched batches: one replay of a graph runs levels level_base + k

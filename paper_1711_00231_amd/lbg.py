@@ -16,9 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbg.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EOVERFLOW, EINTERNAL, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
-AUTO, NODE, EDGE, BALANCED, BINNED, EDGE_NOCHUNK, HIER, SLICED = 0, 1, 2, 3, 4, 5, 6, 7
+AUTO, NODE, EDGE, BALANCED, BINNED, EDGE_NOCHUNK, HIER, SLICED, SPLIT = 0, 1, 2, 3, 4, 5, 6, 7, 8
 STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED, "binned": BINNED,
-              "edge_nochunk": EDGE_NOCHUNK, "hier": HIER, "sliced": SLICED}
+              "edge_nochunk": EDGE_NOCHUNK, "hier": HIER, "sliced": SLICED,
+              "split": SPLIT}
 BFS_INF = 2**31 - 1
 SSSP_INF = 2**32 - 1
 
@@ -93,6 +94,18 @@ def _load():
     lib.lbg_bfs_sliced.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
     lib.lbg_sssp_sliced.restype = ctypes.c_int
     lib.lbg_sssp_sliced.argtypes = [vp, vp, vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
+    lib.lbg_split_scratch_bytes.restype = sz
+    lib.lbg_split_scratch_bytes.argtypes = [i32]
+    lib.lbg_split_count.restype = ctypes.c_int
+    lib.lbg_split_count.argtypes = [vp, i32, i64, i32, ctypes.POINTER(i64), vp, sz, vp]
+    lib.lbg_split_graph.restype = ctypes.c_int
+    lib.lbg_split_graph.argtypes = [vp, vp, vp, i32, i64, i32, i64, vp, vp, vp, vp, vp, sz, vp]
+    lib.lbg_split_workspace_bytes.restype = sz
+    lib.lbg_split_workspace_bytes.argtypes = [i32, i64, i64, i32]
+    lib.lbg_bfs_split.restype = ctypes.c_int
+    lib.lbg_bfs_split.argtypes = [vp, vp, vp, i32, i64, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
+    lib.lbg_sssp_split.restype = ctypes.c_int
+    lib.lbg_sssp_split.argtypes = [vp, vp, vp, vp, i32, i64, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
     lib.lbg_validate_csr.restype = ctypes.c_int
     lib.lbg_validate_csr.argtypes = [vp, vp, i32, i64, vp, sz, vp]
     lib.lbg_last_error.restype = ctypes.c_char_p
@@ -183,6 +196,7 @@ class DeviceGraph:
     host_offsets: object = None  # numpy copy, used to size batched solves
     sliced: "SlicedGraph | None" = None
     packed: "tuple | None" = None  # (arcs tensor, wbits) from lbg_pack_arcs
+    split: "SplitGraph | None" = None
 
     @property
     def n(self) -> int:
@@ -232,6 +246,20 @@ class DeviceGraph:
             self.sliced = slice_graph(self, stream=stream)
         return self.sliced
 
+    def ensure_split(self, mdt: int | None = None, stream=None) -> "SplitGraph":
+        """The split graph for split size ``mdt`` (None: the histogram rule
+        of lbg_degree_mdt), rebuilt when a different size is asked for."""
+        if mdt is None:
+            if self.split is not None and self.split.auto:
+                return self.split
+            mdt_v, auto = degree_mdt(self, stream=stream)[0], True
+        else:
+            mdt_v, auto = int(mdt), False
+        if self.split is None or self.split.mdt != mdt_v:
+            self.split = split_graph(self, mdt_v, stream=stream)
+        self.split.auto = auto
+        return self.split
+
     def ensure_coo(self) -> torch.Tensor:
         if self.coo_src is None:
             deg = (self.offsets[1:] - self.offsets[:-1]).to(torch.int64)
@@ -278,6 +306,51 @@ def slice_graph(g: DeviceGraph, stream=None) -> SlicedGraph:
     return SlicedGraph(so, cols, w, g.n, g.m)
 
 
+@dataclass
+class SplitGraph:
+    """The graph with every node of more than ``mdt`` out-arcs cut into
+    pieces held by child nodes (lbg_split_graph): split_offsets[n + children
+    + 1], child_base[n + 1], cols, weights."""
+
+    split_offsets: torch.Tensor
+    child_base: torch.Tensor
+    cols: torch.Tensor
+    weights: torch.Tensor | None
+    n: int
+    m: int
+    mdt: int
+    children: int
+    auto: bool = False
+
+
+def split_count(g: DeviceGraph, mdt: int, stream=None) -> int:
+    """Number of child nodes node splitting with split size ``mdt`` makes."""
+    dev = g.offsets.device
+    scratch = _ws(None, int(lib.lbg_split_scratch_bytes(g.n)), dev)
+    c = ctypes.c_int64(0)
+    _check(lib.lbg_split_count(_ptr(g.offsets), g.n, g.m, int(mdt), ctypes.byref(c), _ptr(scratch),
+                               scratch.numel(), _stream(stream)))
+    return int(c.value)
+
+
+def split_graph(g: DeviceGraph, mdt: int, stream=None) -> SplitGraph:
+    dev = g.offsets.device
+    children = split_count(g, mdt, stream)
+    scratch = _ws(None, int(lib.lbg_split_scratch_bytes(g.n)), dev)
+    so = torch.empty(g.n + children + 1, dtype=torch.int32, device=dev)
+    cb = torch.empty(g.n + 1, dtype=torch.int32, device=dev)
+    cols = torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+    w = None if g.weights is None else torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+    _check(lib.lbg_split_graph(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(mdt), children,
+                               _ptr(so), _ptr(cb), _ptr(cols), _ptr(w), _ptr(scratch), scratch.numel(),
+                               _stream(stream)))
+    return SplitGraph(so, cb, cols, w, g.n, g.m, int(mdt), children)
+
+
+def split_workspace_bytes(n: int, m: int, children: int, sssp: bool = False) -> int:
+    return int(lib.lbg_split_workspace_bytes(n, m, children, int(sssp)))
+
+
 class Workspace:
     """Caller-owned device workspace, grown on demand and reused."""
 
@@ -302,17 +375,24 @@ def _ws(workspace, nbytes, device):
 
 
 def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None = None,
-        workspace: Workspace | None = None, stats: bool = False, stream=None):
+        workspace: Workspace | None = None, stats: bool = False, stream=None, mdt: int | None = None):
     """Levels from ``src`` (int32, INT32_MAX = unreachable).  Returns the
-    tensor, or (tensor, stats dict) if ``stats``."""
+    tensor, or (tensor, stats dict) if ``stats``.  ``mdt``: split size of
+    the 'split' strategy (None: the histogram rule)."""
     s = _strategy(strategy)
     if out is None:
         out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
-    need = workspace_bytes(g.n, g.m, s, False)
+    need = workspace_bytes(g.n, g.m, s, False) if s != SPLIT else 0  # sized below
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
-    if s == SLICED:
+    if s == SPLIT:
+        sp = g.ensure_split(mdt, stream=stream)
+        ws = _ws(workspace, split_workspace_bytes(g.n, g.m, sp.children, False), g.offsets.device)
+        rc = lib.lbg_bfs_split(_ptr(sp.split_offsets), _ptr(sp.child_base), _ptr(sp.cols), g.n, sp.children,
+                               g.m, int(src), _ptr(out), _ptr(ws), ws.numel(),
+                               ctypes.byref(st) if stats else None, _stream(stream))
+    elif s == SLICED:
         sg = g.ensure_sliced(stream)
         rc = lib.lbg_bfs_sliced(_ptr(g.offsets), _ptr(sg.slice_offsets), _ptr(sg.cols), g.n, g.m, int(src),
                                 _ptr(out), _ptr(ws), ws.numel(), ctypes.byref(st) if stats else None,
@@ -325,10 +405,12 @@ def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None 
 
 
 def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None = None,
-         workspace: Workspace | None = None, stats: bool = False, stream=None, packed: bool = False):
+         workspace: Workspace | None = None, stats: bool = False, stream=None, packed: bool = False,
+         mdt: int | None = None):
     """Distances from ``src`` as an int32 tensor holding uint32 bit patterns
     (use ``.view(torch.uint32)``; UINT32_MAX = unreachable).  ``packed``:
-    balanced strategy on the packed arc words (lbg_sssp_packed)."""
+    balanced strategy on the packed arc words (lbg_sssp_packed).  ``mdt``:
+    split size of the 'split' strategy (None: the histogram rule)."""
     s = _strategy(strategy)
     if packed and s not in (AUTO, BALANCED):
         raise ValueError("packed arcs run the balanced strategy")
@@ -336,7 +418,7 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
         raise ValueError("sssp needs weights")
     if out is None:
         out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
-    need = workspace_bytes(g.n, g.m, s, True)
+    need = workspace_bytes(g.n, g.m, s, True) if s != SPLIT else 0  # sized below
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
@@ -344,6 +426,14 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
         arcs, wbits = g.ensure_packed(stream)
         rc = lib.lbg_sssp_packed(_ptr(g.offsets), _ptr(arcs), wbits, g.n, g.m, int(src), _ptr(out), _ptr(ws),
                                  ws.numel(), ctypes.byref(st) if stats else None, _stream(stream))
+    elif s == SPLIT:
+        sp = g.ensure_split(mdt, stream=stream)
+        if sp.weights is None:
+            raise ValueError("the split graph was built without weights")
+        ws = _ws(workspace, split_workspace_bytes(g.n, g.m, sp.children, True), g.offsets.device)
+        rc = lib.lbg_sssp_split(_ptr(sp.split_offsets), _ptr(sp.child_base), _ptr(sp.cols), _ptr(sp.weights),
+                                g.n, sp.children, g.m, int(src), _ptr(out), _ptr(ws), ws.numel(),
+                                ctypes.byref(st) if stats else None, _stream(stream))
     elif s == SLICED:
         sg = g.ensure_sliced(stream)
         if sg.weights is None:

@@ -63,6 +63,16 @@ def test_workspace_formulas():
     assert lbgmod.workspace_bytes(n, m, "sliced", False) == exp_sliced(bfs_state)
     assert lbgmod.workspace_bytes(n, m, "sliced", True) == exp_sliced(sssp_state)
     assert lbgmod.workspace_bytes(n, 0, "sliced", True) == ctl + sssp_state + 2 * (3 * al(4 * 9) + al(4 * 9 * 2))
+    # split graph: worklists of n + children entries (the bound C = m when
+    # the child count is not given)
+    exp_split = lambda c, state: ctl + state + 2 * (3 * al(4 * (n + c)) + al(4 * tiles))
+    assert lbgmod.workspace_bytes(n, m, "split", False) == exp_split(m, bfs_state)
+    for c in (0, 17, 5000, m):
+        assert lbgmod.split_workspace_bytes(n, m, c, False) == exp_split(c, bfs_state)
+        assert lbgmod.split_workspace_bytes(n, m, c, True) == exp_split(c, sssp_state)
+    assert lbgmod.split_workspace_bytes(n, m, m + 1, False) == 0
+    assert lbgmod.split_workspace_bytes(n, m, -1, False) == 0
+    assert lbgmod.split_workspace_bytes(0, m, 0, False) == 0
     # CSR strategies stay O(n + m / tile); the edge one grows with m
     assert lbgmod.workspace_bytes(n, 50 * m, "balanced", False) < lbgmod.workspace_bytes(n, 50 * m, "edge", False) / 10
     # invalid arguments
@@ -96,8 +106,9 @@ def _sssp(n=10, m=20, src=0, weights=FAKE, strategy=lbgmod.BALANCED, coo=None, w
     (dict(out=None), lbgmod.EINVAL),
     (dict(ws=None), lbgmod.EINVAL),
     (dict(cols=None), lbgmod.EINVAL),
-    (dict(strategy=8), lbgmod.EINVAL),
+    (dict(strategy=9), lbgmod.EINVAL),
     (dict(strategy=lbgmod.SLICED), lbgmod.EINVAL),        # only through lbg_bfs_sliced
+    (dict(strategy=lbgmod.SPLIT), lbgmod.EINVAL),         # only through lbg_bfs_split
     (dict(strategy=-2), lbgmod.EINVAL),
     (dict(strategy=lbgmod.EDGE_NOCHUNK), lbgmod.EINVAL),  # no coo_src
     (dict(strategy=lbgmod.EDGE), lbgmod.EINVAL),          # no coo_src
@@ -228,3 +239,51 @@ def test_packed_argument_errors():
     assert sp(arcs=None) == lbgmod.EINVAL
     assert sp(src=10) == lbgmod.ERANGE
     assert sp(wsb=16) == lbgmod.ENOMEM
+
+
+def test_split_scratch_and_argument_errors():
+    al = lambda x: (x + 255) // 256 * 256
+    for n in (1, 4096, 4097, 10**6, 2**31 - 1):
+        assert lib.lbg_split_scratch_bytes(n) == al(12 * ((n + 4095) // 4096 + 1))
+    assert lib.lbg_split_scratch_bytes(0) == 0
+    c = ctypes.c_int64(-1)
+    cnt = lambda n=10, m=20, mdt=4, offsets=FAKE, co=ctypes.byref(c), sc=WS, scb=64: \
+        lib.lbg_split_count(offsets, n, m, mdt, co, sc, scb, None)
+    assert cnt(n=0) == lbgmod.EINVAL
+    assert cnt(m=-1) == lbgmod.ERANGE
+    assert cnt(m=2**31) == lbgmod.ERANGE
+    assert cnt(mdt=-1) == lbgmod.EINVAL
+    assert cnt(offsets=None) == lbgmod.EINVAL
+    assert cnt(co=None) == lbgmod.EINVAL
+    assert cnt(sc=None) == lbgmod.EINVAL
+    assert cnt(sc=ctypes.c_void_p(0x10010)) == lbgmod.EINVAL
+    assert cnt(scb=16) == lbgmod.ENOMEM        # 12 bytes per 4096 nodes + the totals
+    assert c.value == -1                       # untouched on error
+
+    def grp(n=10, m=20, offsets=FAKE, cols=FAKE, w=FAKE, so=FAKE, cb=FAKE, cout=FAKE, wout=FAKE, scb=16):
+        return lib.lbg_split_graph(offsets, cols, w, n, m, 4, 3, so, cb, cout, wout, WS, scb, None)
+
+    assert grp(so=None) == lbgmod.EINVAL
+    assert grp(cb=None) == lbgmod.EINVAL
+    assert grp(cols=None) == lbgmod.EINVAL
+    assert grp(cout=None) == lbgmod.EINVAL
+    assert grp(wout=None) == lbgmod.EINVAL     # weights without weights_out
+    assert grp(w=None) == lbgmod.EINVAL        # weights_out without weights
+    assert grp(n=0) == lbgmod.EINVAL
+    assert grp(scb=16) == lbgmod.ENOMEM
+
+    ws = 1 << 40
+    bs = lambda n=10, children=3, m=20, src=0, cb=FAKE, wsb=ws: \
+        lib.lbg_bfs_split(FAKE, cb, FAKE, n, children, m, src, FAKE, WS, wsb, None, None)
+    assert bs(cb=None) == lbgmod.EINVAL
+    assert bs(children=21) == lbgmod.ERANGE    # more children than arcs
+    assert bs(children=-1) == lbgmod.ERANGE
+    assert bs(src=10) == lbgmod.ERANGE
+    assert bs(n=0) == lbgmod.EINVAL
+    assert bs(wsb=64) == lbgmod.ENOMEM
+    assert "children" in (bs(children=21), lib.lbg_last_error().decode())[1]
+    ss = lambda w=FAKE, cb=FAKE, wsb=ws: \
+        lib.lbg_sssp_split(FAKE, cb, FAKE, w, 10, 3, 20, 0, FAKE, WS, wsb, None, None)
+    assert ss(w=None) == lbgmod.EINVAL
+    assert ss(cb=None) == lbgmod.EINVAL
+    assert ss(wsb=64) == lbgmod.ENOMEM

@@ -16,8 +16,8 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 from paper_1711_00231_amd import lbg  # noqa: E402  (fails loudly if liblbg.so is missing)
 
-STRATS = ["node", "edge", "balanced", "binned", "hier", "edge_nochunk", "sliced"]
-FULL_STRATS = ["node", "edge", "balanced", "binned", "hier", "sliced"]  # the ablation is too slow at full size
+STRATS = ["node", "edge", "balanced", "binned", "hier", "edge_nochunk", "sliced", "split"]
+FULL_STRATS = ["node", "edge", "balanced", "binned", "hier", "sliced", "split"]  # the ablation is too slow at full size
 O = oracle.get()
 
 
@@ -333,6 +333,89 @@ def test_slice_graph_groups_adjacency(which):
     assert sb.weights is None and np.array_equal(sb.cols.cpu().numpy()[: g.m], g.cols[order])
 
 
+def _expected_split(g, mdt):
+    """The split graph written out from the node-splitting piece sizes of the
+    oracle: parents' own pieces first (node order), then every child piece
+    (parent order, piece order); mdt 0 leaves every node whole."""
+    deg = g.degrees.astype(np.int64)
+    pieces = [O.ns_pieces(int(d), mdt) if mdt > 0 else np.array([d], np.int64) for d in deg]
+    own = np.array([p[0] for p in pieces], np.int64)
+    kids = [p[1:] for p in pieces]
+    nkids = np.array([k.size for k in kids], np.int64)
+    child_base = np.concatenate([[0], np.cumsum(nkids)])
+    P = int(own.sum())
+    kid_sizes = np.concatenate(kids + [np.zeros(0, np.int64)])
+    so = np.concatenate([np.concatenate([[0], np.cumsum(own)])[:-1], P + np.concatenate([[0], np.cumsum(kid_sizes)])])
+    off = g.offsets.astype(np.int64)
+    idx = np.arange(g.m, dtype=np.int64)
+    node = np.repeat(np.arange(g.n), deg)
+    first = idx < off[node] + own[node]
+    order = np.concatenate([idx[first], idx[~first]])  # stable: node order, then arc order
+    return so, child_base, order
+
+
+@pytest.mark.parametrize("mdt", [0, 1, 2, 7, 64])
+@pytest.mark.parametrize("which", ["uniform", "rmat", "hub", "tiny"])
+def test_split_graph_layout(which, mdt):
+    """lbg_split_graph against the split graph built from the oracle's piece
+    sizes: offsets, child table and arc order, exactly."""
+    rng = np.random.default_rng(4)
+    if which == "uniform":
+        g = graphgen.uniform(12)
+    elif which == "rmat":
+        g = graphgen.rmat(13)
+    elif which == "hub":
+        n = 5000
+        src = np.concatenate([np.zeros(9000, np.int64), np.full(130, 7), rng.integers(0, n, 9000)])
+        dst = rng.integers(0, n, src.size)
+        g = graphgen.from_edges(n, src, dst, rng.integers(1, 9, src.size), "hub")
+    else:
+        g = graphgen.from_edges(3, [0, 0, 2], [2, 1, 0], [5, 6, 7], "tiny")
+    dg = _dev(g)
+    so, cb, order = _expected_split(g, mdt)
+    assert lbg.split_count(dg, mdt) == cb[-1]
+    sp = lbg.split_graph(dg, mdt)
+    assert sp.children == cb[-1] and sp.split_offsets.numel() == g.n + sp.children + 1
+    assert np.array_equal(sp.split_offsets.cpu().numpy().astype(np.int64), so)
+    assert np.array_equal(sp.child_base.cpu().numpy().astype(np.int64), cb)
+    assert np.array_equal(sp.cols.cpu().numpy()[: g.m], g.cols[order])
+    assert np.array_equal(sp.weights.cpu().numpy().view(np.uint32)[: g.m], g.weights[order])
+    bg = lbg.DeviceGraph(dg.offsets, dg.cols, None)  # BFS-only: no weights in, none out
+    sb = lbg.split_graph(bg, mdt)
+    assert sb.weights is None and np.array_equal(sb.cols.cpu().numpy()[: g.m], g.cols[order])
+
+
+@pytest.mark.parametrize("mdt", [1, 2, 7, 64, 5000])
+def test_split_sizes(mdt):
+    """Node splitting at split sizes from every arc its own child (1) to no
+    split at all (5000): the same results as the oracle, and BFS frontier
+    entries = the pieces of every reached node with arcs."""
+    rng = np.random.default_rng(8)
+    n = 4000
+    src = np.concatenate([np.zeros(3000, np.int64), np.full(700, 3), rng.integers(0, n, 12000)])
+    dst = rng.integers(0, n, src.size)
+    hub = graphgen.from_edges(n, src, dst, rng.integers(0, 30, src.size), "hub")
+    cases = [(hub, [0, 3, 11]), (graphgen.rmat(13), None), (graphgen.grid(40), [0])]
+    cases += [(gg, [s]) for gg, s in pins.tiny_graphs(count=8, seed=9)]
+    for g, srcs in cases:
+        if srcs is None:
+            srcs = graphgen.sources(g, 2, graphgen.FAMILY_RMAT)
+        dg = _dev(g)
+        for s in srcs:
+            exp_l = O.bfs(g.offsets, g.cols, int(s))
+            lv, st = _gpu_bfs(dg, s, "split", mdt=mdt, stats=True)
+            assert np.array_equal(lv, exp_l), (g.name, s, mdt)
+            reached = exp_l != pins.BFS_INF
+            deg = g.degrees.astype(np.int64)
+            pcs = np.where(deg > mdt, (deg + mdt - 1) // mdt, 1)
+            assert st["frontier_entries"] == int(pcs[reached & (deg > 0)].sum()), (g.name, s, mdt)
+            assert st["edges_scanned"] == g.reached_arcs(reached)
+            # levels counts frontiers with at least one out-arc
+            assert st["levels"] == int(exp_l[reached & (deg > 0)].max(initial=-1)) + 1
+            d = _gpu_sssp(dg, s, "split", mdt=mdt)
+            assert np.array_equal(d, O.dijkstra(g.offsets, g.cols, g.weights, int(s))), (g.name, s, mdt)
+
+
 def test_repeat_runs_identical():
     """Relaxation order differs from run to run; results must not."""
     g = graphgen.rmat(14)
@@ -353,7 +436,7 @@ def test_stats_and_validate():
     for strat in ("node", "balanced"):
         lv, st = _gpu_bfs(dg, s, strat, stats=True)
         assert np.array_equal(lv, lv_exp)
-        assert st["levels"] == int(lv_exp[reached].max()) + 1
+        assert st["levels"] == int(lv_exp[reached & (g.degrees > 0)].max()) + 1
         assert st["edges_scanned"] == g.reached_arcs(reached)
         assert st["updates"] == int(reached.sum()) - 1
         assert st["frontier_entries"] == int((reached & (g.degrees > 0)).sum())
@@ -369,7 +452,7 @@ def test_stats_and_validate():
             lbg.set_slice_min(smin)
             lv, st = _gpu_bfs(dg, s, "sliced", stats=True)
             assert np.array_equal(lv, lv_exp)
-            assert st["levels"] == int(lv_exp[reached].max()) + 1
+            assert st["levels"] == int(lv_exp[reached & (g.degrees > 0)].max()) + 1
             assert st["edges_scanned"] == g.reached_arcs(reached)
             assert st["updates"] == int(reached.sum()) - 1
             split = g.degrees >= smin
