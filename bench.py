@@ -438,8 +438,9 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
     max_rows = 6 * max([g.n for _, g in small] + [1]) + 16 * NC
     eng = lbg.Engine(dg, max_queries=64, max_rows=max_rows,
                      max_level_arcs=min(2**32 - 1, 8 * (u.m + R * MC)))
-    big = {nm: singles[nm] for nm, g in zip(names, resident) if g.m >= big_arcs}
-    lane = serve.gpu_plain_lane(big, big_arcs) if big else None
+    # the plain lane holds every resident instance: large ones always go
+    # there, small ones only when the engine and the lane are both idle
+    lane = serve.gpu_plain_lane(singles, big_arcs)
 
     def plain_serve(reqs):
         """The same arrivals served FCFS by one plain call per request (upload
@@ -466,7 +467,7 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         reqs = serve.poisson_requests(qps, requests_per_point, inst, upload_graphs=uploads,
                                       upload_share=0.25, seed=int(frac * 1000), sources=srcs)
         arena = serve.UploadArena(dg, u.n, u.m, R, NC, MC)
-        rep = serve.Server(eng, inst, upload=arena, plain=lane).run(reqs)
+        rep = serve.Server(eng, inst, upload=arena, plain=lane, idle_bypass=True).run(reqs)
         s = rep.summary()
         s["offered_qps"] = round(qps, 2)
         s["fraction_of_plain_saturation"] = frac
@@ -483,8 +484,9 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
                         f"Poisson arrivals, 70% BFS / 30% SSSP, 25% uploads; "
                         f"{requests_per_point} requests per point; gteps counts instance arcs; "
                         f"instances of >= {big_arcs} arcs are served by plain solves on a second "
-                        f"stream, the rest are batched; plain_* = the same arrivals served FCFS "
-                        f"by one plain call each"}
+                        f"stream, the rest are batched unless the engine and that stream are both "
+                        f"idle (then a resident query runs plain: 'bypassed'); plain_* = the same "
+                        f"arrivals served FCFS by one plain call each"}
 
 
 def main():

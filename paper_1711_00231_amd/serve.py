@@ -23,7 +23,11 @@ Admission is size-aware when a PlainLane is given: a query on a large
 resident instance already fills the GPU by itself, so batching it would only
 add per-level synchronisation; such queries are served first-come
 first-served by one plain solve each, on a stream and host thread of their
-own, while the engine keeps batching the small ones on the same GPU.
+own, while the engine keeps batching the small ones on the same GPU.  With
+idle_bypass, a query on a small resident instance that arrives while both
+the engine and the plain lane are idle is also given to the lane: alone on
+the GPU, one plain solve finishes sooner than the engine's level-by-level
+batch, and the next arrivals are batched as before.
 
 The engine and the plain solver are injected: anything with
 submit/step/release/rows works, which is how the scheduling logic is tested
@@ -94,6 +98,7 @@ class Request:
     length: int = 0
     region: int = -1
     arcs: int = 0
+    bypass: bool = False    # a small query given to the idle plain lane
     result: np.ndarray | None = None
 
     @property
@@ -123,6 +128,9 @@ class ServeReport:
             k = sum(r.status == st for r in self.dropped)
             if k:
                 out[st] = k
+        k = sum(r.bypass for r in self.completed)
+        if k:
+            out["bypassed"] = k
         if lat.size:
             out.update({"p50_ms": round(float(np.percentile(lat, 50)), 4),
                         "p99_ms": round(float(np.percentile(lat, 99)), 4),
@@ -137,11 +145,14 @@ class PlainLane:
     plain solve each from a worker thread.  solve(request, keep) runs the
     query to completion (the GPU binding releases the interpreter lock
     meanwhile) and returns its result row when keep is true; `big_arcs` is
-    the size from which an instance goes here."""
+    the size from which an instance goes here.  names: the resident
+    instances solve() can serve (None: all); a server with idle_bypass
+    sends small ones here only while everything is idle."""
 
-    def __init__(self, solve, big_arcs: int):
+    def __init__(self, solve, big_arcs: int, names=None):
         self.solve = solve
         self.big_arcs = int(big_arcs)
+        self.names = None if names is None else set(names)
         self._q: queue.Queue = queue.Queue()
         self._lock = threading.Lock()
         self._done: list = []
@@ -151,6 +162,13 @@ class PlainLane:
 
     def wants(self, arcs: int) -> bool:
         return arcs >= self.big_arcs
+
+    def can_solve(self, instance: str) -> bool:
+        return self.names is None or instance in self.names
+
+    def idle(self) -> bool:
+        with self._lock:
+            return self._pending == 0
 
     def start(self, clock, t0: float, keep_results: bool) -> None:
         def work():
@@ -211,14 +229,17 @@ class Server:
     CSR).  upload: optional UploadArena for per-request graphs.  plain:
     optional PlainLane for queries on large resident instances.
     timeout: default longest wait for admission, in seconds (None: no limit;
-    a request's own timeout takes precedence).
+    a request's own timeout takes precedence).  idle_bypass: give a small
+    resident query to the plain lane when the lane is idle and (True or
+    "idle") the engine has nothing in flight, or ("lane") whatever the
+    engine is running; False: small queries always go to the engine.
     """
 
     ADMITTED, WAIT, REJECT = 0, 1, 2
 
     def __init__(self, engine, instances: dict, upload=None, levels_per_step: int = 1,
                  keep_results: bool = False, plain: PlainLane | None = None,
-                 timeout: float | None = None):
+                 timeout: float | None = None, idle_bypass: bool = False):
         self.engine = engine
         self.instances = instances
         self.upload = upload
@@ -226,6 +247,10 @@ class Server:
         self.keep_results = keep_results
         self.plain = plain
         self.timeout = timeout
+        modes = {False: "", True: "idle", "idle": "idle", "lane": "lane"}
+        if idle_bypass not in modes:
+            raise ValueError(f"idle_bypass must be False, True, 'idle' or 'lane' (got {idle_bypass!r})")
+        self.idle_bypass = modes[idle_bypass]
         self.rows = RowAllocator(engine.max_rows)
         self.inflight: dict[int, Request] = {}
         self._cancel_lock = threading.Lock()
@@ -255,8 +280,9 @@ class Server:
         if r.instance is not None:
             inst = self.instances[r.instance]
             lo, hi, arcs = inst.lo, inst.hi, inst.arcs
-            if self.plain is not None and self.plain.wants(arcs):
+            if self.plain is not None and (self.plain.wants(arcs) or self._bypass(r)):
                 r.admitted, r.arcs, r.length = now, arcs, hi - lo
+                r.bypass = not self.plain.wants(arcs)
                 self.plain.submit(r)
                 return self.ADMITTED
         else:
@@ -281,6 +307,11 @@ class Server:
         r.slot, r.row, r.length, r.arcs, r.admitted = slot, row, hi - lo, arcs, now
         self.inflight[slot] = r
         return self.ADMITTED
+
+    def _bypass(self, r: Request) -> bool:
+        if not self.idle_bypass or not self.plain.can_solve(r.instance) or not self.plain.idle():
+            return False
+        return self.idle_bypass == "lane" or not self.inflight
 
     def _expired(self, r: Request, now: float) -> bool:
         t = r.timeout if r.timeout is not None else self.timeout
@@ -462,7 +493,8 @@ class UploadArena:
 def gpu_plain_lane(graphs: dict, big_arcs: int) -> PlainLane:
     """A PlainLane over resident device graphs (instance name -> DeviceGraph
     with local node ids): each query runs as one balanced BFS/SSSP solve on
-    a stream of its own."""
+    a stream of its own.  Instances below big_arcs given here are served by
+    the lane only through a server's idle bypass."""
     import torch
 
     from . import lbg
@@ -484,4 +516,4 @@ def gpu_plain_lane(graphs: dict, big_arcs: int) -> PlainLane:
         with torch.cuda.stream(stream):
             return out[: g.n].cpu().numpy()
 
-    return PlainLane(solve, big_arcs)
+    return PlainLane(solve, big_arcs, names=graphs.keys())

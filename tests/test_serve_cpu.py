@@ -322,3 +322,66 @@ def test_plain_lane_skips_cancelled_requests():
     assert sorted(r.rid for r in rep.completed) == [0, 1, 3]
     assert [(r.rid, r.status) for r in rep.dropped] == [(2, "cancelled")]
     _check_results(rep, gs)
+
+
+def _oracle_solve(gs):
+    def solve(r, keep):
+        g = gs[int(r.instance[1:])]
+        if r.kind == serve.KIND_BFS:
+            return O.bfs(g.offsets, g.cols, r.src)
+        return O.dijkstra(g.offsets, g.cols, g.weights, r.src).view(np.int32)
+    return solve
+
+
+@pytest.mark.parametrize("bypass", [False, True])
+def test_idle_bypass_only_when_everything_is_idle(bypass):
+    """With idle_bypass, the first of a burst (engine and lane idle) goes to
+    the plain lane and most of the rest are batched; without it, small
+    instances never leave the engine.  Results are the oracle's either way."""
+    gs, u, inst = _setup()
+    lane = serve.PlainLane(_oracle_solve(gs), big_arcs=1 << 40)  # nothing is big
+    eng = FakeEngine(u, max_queries=4, max_rows=12000)
+    reqs = serve.poisson_requests(1e4, 12, inst, seed=21)
+    rep = serve.Server(eng, inst, keep_results=True, plain=lane, idle_bypass=bypass).run(reqs, replay=True)
+    assert len(rep.completed) == 12 and not eng.slots
+    _check_results(rep, gs)
+    by = [r for r in rep.completed if r.bypass]
+    assert [r.slot < 0 for r in rep.completed] == [r.bypass for r in rep.completed]
+    if bypass:
+        # the burst's first request finds everything idle; while the lane or
+        # the engine is busy the others are batched (a later one may again
+        # find both idle while it waits for engine capacity)
+        assert by[0].rid == reqs[0].rid and len(by) < len(reqs) // 2
+        assert rep.summary()["bypassed"] == len(by)
+    else:
+        assert not by and "bypassed" not in rep.summary()
+
+
+def test_idle_bypass_on_spaced_arrivals_and_names():
+    """Arrivals far apart find everything idle, so each one on an instance the
+    lane holds is bypassed; instances the lane does not hold stay batched."""
+    gs, u, inst = _setup()
+    lane = serve.PlainLane(_oracle_solve(gs), big_arcs=1 << 40, names=["g0", "g2"])
+    eng = FakeEngine(u, max_queries=4, max_rows=12000)
+    reqs = [serve.Request(i, 0.03 * i, serve.KIND_BFS if i % 2 else serve.KIND_SSSP, f"g{i % 3}", 5 + i)
+            for i in range(9)]
+    rep = serve.Server(eng, inst, keep_results=True, plain=lane, idle_bypass=True).run(reqs)
+    assert len(rep.completed) == 9
+    _check_results(rep, gs)
+    for r in rep.completed:
+        assert r.bypass == (r.instance != "g1"), (r.rid, r.instance)
+
+
+def test_bypass_modes():
+    """'lane' bypasses whenever the lane is idle, even with queries in the
+    engine; an unknown mode is refused."""
+    gs, u, inst = _setup()
+    lane = serve.PlainLane(_oracle_solve(gs), big_arcs=1 << 40)
+    eng = FakeEngine(u, max_queries=4, max_rows=12000)
+    srv = serve.Server(eng, inst, keep_results=True, plain=lane, idle_bypass="lane")
+    srv.inflight[0] = object()  # pretend the engine is busy
+    assert srv._bypass(serve.Request(0, 0.0, serve.KIND_BFS, "g0", 1))
+    srv.idle_bypass = "idle"
+    assert not srv._bypass(serve.Request(0, 0.0, serve.KIND_BFS, "g0", 1))
+    with pytest.raises(ValueError, match="idle_bypass"):
+        serve.Server(eng, inst, plain=lane, idle_bypass="always")
