@@ -467,7 +467,8 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         reqs = serve.poisson_requests(qps, requests_per_point, inst, upload_graphs=uploads,
                                       upload_share=0.25, seed=int(frac * 1000), sources=srcs)
         arena = serve.UploadArena(dg, u.n, u.m, R, NC, MC)
-        rep = serve.Server(eng, inst, upload=arena, plain=lane, idle_bypass=True).run(reqs)
+        rep = serve.Server(eng, inst, upload=arena, plain=lane, idle_bypass=True,
+                           levels_per_step=2).run(reqs)
         s = rep.summary()
         s["offered_qps"] = round(qps, 2)
         s["fraction_of_plain_saturation"] = frac
@@ -485,7 +486,8 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
                         f"{requests_per_point} requests per point; gteps counts instance arcs; "
                         f"instances of >= {big_arcs} arcs are served by plain solves on a second "
                         f"stream, the rest are batched unless the engine and that stream are both "
-                        f"idle (then a resident query runs plain: 'bypassed'); plain_* = the same "
+                        f"idle (then a resident query runs plain: 'bypassed'); the engine advances "
+                        f"2 levels per step; plain_* = the same "
                         f"arrivals served FCFS by one plain call each"}
 
 
