@@ -278,6 +278,41 @@ int lbg_sssp_split(const int32_t* split_offsets, const int32_t* child_base, cons
                    uint32_t* dist_out, void* workspace, size_t workspace_bytes, lbg_stats* stats,
                    void* stream);
 
+/* ------------------------------------------------------------------------
+ * Degree-class ordered copy for SSSP (the balanced strategy of Section III-A
+ * on a renumbered copy of the graph; a memory layout, the arithmetic is
+ * unchanged).
+ *
+ * lbg_order_graph: renumbers the nodes by degree class, largest first (the
+ * class of out-degree d is its bit length: 0 for d = 0, 1 for d = 1, 2 for
+ * 2..3, ...; original order within a class) and writes
+ *   new_id[n] int32: the new id of original node v;
+ *   order_offsets[n+1], order_cols[m], order_weights[m]: the same graph in
+ *     new ids; the arcs of new node k are those of the original node, with
+ *     destinations renamed, ordered by destination class (largest first) and
+ *     by input position within a class (ascending new id when the input
+ *     adjacency lists are sorted).
+ * weights and order_weights are both NULL or both given (when m > 0).
+ * scratch: device buffer of lbg_order_scratch_bytes(n) bytes (about 4n +
+ * 32 bytes per 32 nodes), 256-byte aligned, overwritten.  Outputs are device
+ * buffers the caller allocates, not overlapping the inputs; offsets outside
+ * [0, m] are clamped and destinations outside [0, n) are copied unchanged
+ * (lbg_validate_csr first on untrusted input).  Returns when the outputs are
+ * written.
+ *
+ * lbg_sssp_ordered: lbg_sssp with strategy LBG_BALANCED on the ordered copy:
+ * src and dist_out are in ORIGINAL ids (the source is renamed and the
+ * distances gathered back through new_id on the device), so results equal
+ * lbg_sssp's on the original graph.  Workspace:
+ * lbg_workspace_bytes(n, m, LBG_BALANCED, 1). */
+size_t lbg_order_scratch_bytes(int32_t n);
+int lbg_order_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, int32_t* order_offsets, int32_t* order_cols, uint32_t* order_weights,
+                    int32_t* new_id, void* scratch, size_t scratch_bytes, void* stream);
+int lbg_sssp_ordered(const int32_t* order_offsets, const int32_t* order_cols, const uint32_t* order_weights,
+                     const int32_t* new_id, int32_t n, int64_t m, int32_t src, uint32_t* dist_out,
+                     void* workspace, size_t workspace_bytes, lbg_stats* stats, void* stream);
+
 /* Structural check of a CSR graph on the device: offsets[0] == 0,
  * non-decreasing offsets, offsets[n] == m, every col in [0, n).  Needs
  * lbg_workspace_bytes(n, m, LBG_NODE, 0) bytes of workspace.  Returns LBG_OK

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "liblbg.so")
 SOURCES = [os.path.join(HERE, "csrc", "lbg.hip")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("lbg_device.hpp", "lbg_kernels.hpp", "lbg_sliced.hpp",
-                                                                    "lbg_split.hpp")] + \
+                                                                    "lbg_split.hpp", "lbg_order.hpp")] + \
     [os.path.join(ROOT, "include", "lbg.h")]
 
 HIPCC_FLAGS = [

@@ -14,6 +14,7 @@
 #include "lbg_kernels.hpp"
 #include "lbg_sliced.hpp"
 #include "lbg_split.hpp"
+#include "lbg_order.hpp"
 
 namespace {
 
@@ -301,6 +302,7 @@ struct Problem {
   int32_t wbits = 0;
   const int32_t* child_base = nullptr;  // lbg_bfs_split / lbg_sssp_split: the split graph's
   int64_t children = 0;                 // child table and child count
+  const int32_t* node_map = nullptr;    // lbg_sssp_ordered: new id of every original node
 };
 
 int check_common(const Problem& P) {
@@ -381,6 +383,7 @@ int solve(const Problem& P) {
   const bool sl = strat == LBG_SLICED;
   const bool split = strat == LBG_SPLIT;
   a.child_base = P.child_base;
+  a.node_map = P.node_map;
   if (sl) {
     a.soff = P.soff;
     a.sliced = 1u;
@@ -1415,6 +1418,66 @@ int lbg_sssp_split(const int32_t* split_offsets, const int32_t* child_base, cons
             LBG_SPLIT, 1, stats, static_cast<hipStream_t>(stream)};
   P.child_base = child_base;
   P.children = children;
+  return solve(P);
+}
+
+size_t lbg_order_scratch_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  const size_t nb = (static_cast<size_t>(n) + lbg::kOrdChunk - 1) / lbg::kOrdChunk;
+  return align_up(sizeof(uint32_t) * (lbg::kOrdClasses * nb + 1)) + align_up(sizeof(uint32_t) * (nb + 1)) +
+         align_up(sizeof(int32_t) * static_cast<size_t>(n));
+}
+
+int lbg_order_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                    int64_t m, int32_t* order_offsets, int32_t* order_cols, uint32_t* order_weights,
+                    int32_t* new_id, void* scratch, size_t scratch_bytes, void* stream) {
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX)
+    return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
+  if (!offsets || !order_offsets || !new_id || !scratch || (m > 0 && (!cols || !order_cols)))
+    return fail(LBG_EINVAL, "null offsets/order_offsets/new_id/scratch/cols/order_cols pointer");
+  if (m > 0 && (weights == nullptr) != (order_weights == nullptr))
+    return fail(LBG_EINVAL, "weights and order_weights must both be given or both be NULL");
+  if (reinterpret_cast<uintptr_t>(scratch) % kAlign)
+    return fail(LBG_EINVAL, "scratch must be %zu-byte aligned", kAlign);
+  if (scratch_bytes < lbg_order_scratch_bytes(n))
+    return fail(LBG_ENOMEM, "scratch has %zu bytes, needs %zu", scratch_bytes, lbg_order_scratch_bytes(n));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t un = static_cast<uint32_t>(n), um = static_cast<uint32_t>(m);
+  const uint32_t nb = static_cast<uint32_t>((static_cast<int64_t>(n) + lbg::kOrdChunk - 1) / lbg::kOrdChunk);
+  char* sc = static_cast<char*>(scratch);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(sc);
+  sc += align_up(sizeof(uint32_t) * (lbg::kOrdClasses * static_cast<size_t>(nb) + 1));
+  uint32_t* sums = reinterpret_cast<uint32_t*>(sc);
+  sc += align_up(sizeof(uint32_t) * (static_cast<size_t>(nb) + 1));
+  int32_t* order = reinterpret_cast<int32_t*>(sc);
+  hipLaunchKernelGGL(lbg::k_ord_count, dim3(nb), dim3(lbg::kBlock), 0, st, offsets, un, um, cnt, nb);
+  hipLaunchKernelGGL(lbg::k_ord_scan, dim3(1), dim3(lbg::kBlock), 0, st, cnt, lbg::kOrdClasses * nb);
+  hipLaunchKernelGGL(lbg::k_ord_scatter, dim3(nb), dim3(lbg::kBlock), 0, st, offsets, un, um,
+                     static_cast<const uint32_t*>(cnt), nb, order, new_id);
+  hipLaunchKernelGGL(lbg::k_ord_deg_sums, dim3(nb), dim3(lbg::kBlock), 0, st, offsets, un, um,
+                     static_cast<const int32_t*>(order), sums);
+  hipLaunchKernelGGL(lbg::k_ord_scan, dim3(1), dim3(lbg::kBlock), 0, st, sums, nb);
+  hipLaunchKernelGGL(lbg::k_ord_offsets, dim3(nb), dim3(lbg::kBlock), 0, st, offsets, un, um,
+                     static_cast<const int32_t*>(order), static_cast<const uint32_t*>(sums), nb, order_offsets);
+  if (m > 0) {
+    const int blocks = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(n) + lbg::kWaves - 1) / lbg::kWaves, 16384));
+    hipLaunchKernelGGL(lbg::k_ord_copy, dim3(blocks), dim3(lbg::kBlock), 0, st, offsets, cols, weights, un, um,
+                       static_cast<const int32_t*>(order), static_cast<const int32_t*>(new_id),
+                       static_cast<const int32_t*>(order_offsets), order_cols, order_weights);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return LBG_OK;
+}
+
+int lbg_sssp_ordered(const int32_t* order_offsets, const int32_t* order_cols, const uint32_t* order_weights,
+                     const int32_t* new_id, int32_t n, int64_t m, int32_t src, uint32_t* dist_out,
+                     void* workspace, size_t workspace_bytes, lbg_stats* stats, void* stream) {
+  if (!new_id) return fail(LBG_EINVAL, "null new_id pointer");
+  Problem P{order_offsets, order_cols, order_weights, nullptr, n, m, src, dist_out, workspace, workspace_bytes,
+            LBG_BALANCED, 1, stats, static_cast<hipStream_t>(stream)};
+  P.node_map = new_id;
   return solve(P);
 }
 

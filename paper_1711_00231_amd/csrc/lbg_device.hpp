@@ -135,6 +135,10 @@ struct KArgs {
   // n + child_base[v] .. n + child_base[v + 1] - 1, each holding one piece
   // of v's arcs (null: no split graph).
   const int32_t* child_base;
+  // Degree-class ordered copy: the graph's ids are new ids, node_map[v] is
+  // the new id of original node v; the source is given and the distances
+  // are written in original ids (null: no renaming).
+  const int32_t* node_map;
 };
 
 // Pieces of a node with d out-arcs under split size mdt, and piece k's

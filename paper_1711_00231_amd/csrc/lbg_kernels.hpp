@@ -209,6 +209,7 @@ __device__ __forceinline__ void init_state(const KArgs& a, int32_t src, uint32_t
 
 template <bool kSssp, bool kEdgeWl>
 __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
+  if (a.node_map) src = a.node_map[src];  // the host checked 0 <= src < n
   const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t stride = gridDim.x * kBlock;
   init_state<kSssp>(a, src, gid, stride);
@@ -308,6 +309,13 @@ __global__ __launch_bounds__(kBlock) void k_sssp_finish(KArgs a) {
         return;
   }
   const uint32_t stride = gridDim.x * kBlock;
+  if (a.node_map) {  // distances in original ids
+    for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += stride) {
+      const uint32_t u = static_cast<uint32_t>(a.node_map[v]);
+      a.dist[v] = u < a.n ? static_cast<uint32_t>(a.dstate[u] >> 32) : kSsspInf;
+    }
+    return;
+  }
   for (uint32_t v = blockIdx.x * kBlock + threadIdx.x; v < a.n; v += stride)
     a.dist[v] = static_cast<uint32_t>(a.dstate[v] >> 32);
 }

@@ -106,6 +106,12 @@ def _load():
     lib.lbg_bfs_split.argtypes = [vp, vp, vp, i32, i64, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
     lib.lbg_sssp_split.restype = ctypes.c_int
     lib.lbg_sssp_split.argtypes = [vp, vp, vp, vp, i32, i64, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
+    lib.lbg_order_scratch_bytes.restype = sz
+    lib.lbg_order_scratch_bytes.argtypes = [i32]
+    lib.lbg_order_graph.restype = ctypes.c_int
+    lib.lbg_order_graph.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp, vp, vp, sz, vp]
+    lib.lbg_sssp_ordered.restype = ctypes.c_int
+    lib.lbg_sssp_ordered.argtypes = [vp, vp, vp, vp, i32, i64, i32, vp, vp, sz, ctypes.POINTER(Stats), vp]
     lib.lbg_validate_csr.restype = ctypes.c_int
     lib.lbg_validate_csr.argtypes = [vp, vp, i32, i64, vp, sz, vp]
     lib.lbg_last_error.restype = ctypes.c_char_p
@@ -197,6 +203,7 @@ class DeviceGraph:
     sliced: "SlicedGraph | None" = None
     packed: "tuple | None" = None  # (arcs tensor, wbits) from lbg_pack_arcs
     split: "SplitGraph | None" = None
+    ordered: "OrderedGraph | None" = None
 
     @property
     def n(self) -> int:
@@ -259,6 +266,12 @@ class DeviceGraph:
             self.split = split_graph(self, mdt_v, stream=stream)
         self.split.auto = auto
         return self.split
+
+    def ensure_ordered(self, stream=None) -> "OrderedGraph":
+        """The degree-class ordered copy (lbg_order_graph), built once."""
+        if self.ordered is None:
+            self.ordered = order_graph(self, stream=stream)
+        return self.ordered
 
     def ensure_coo(self) -> torch.Tensor:
         if self.coo_src is None:
@@ -347,6 +360,31 @@ def split_graph(g: DeviceGraph, mdt: int, stream=None) -> SplitGraph:
     return SplitGraph(so, cb, cols, w, g.n, g.m, int(mdt), children)
 
 
+@dataclass
+class OrderedGraph:
+    """The graph renumbered by degree class, largest first (lbg_order_graph):
+    offsets, cols, weights in new ids and new_id[v] of every original node."""
+
+    offsets: torch.Tensor
+    cols: torch.Tensor
+    weights: torch.Tensor | None
+    new_id: torch.Tensor
+    n: int
+    m: int
+
+
+def order_graph(g: DeviceGraph, stream=None) -> OrderedGraph:
+    dev = g.offsets.device
+    scratch = torch.empty(max(int(lib.lbg_order_scratch_bytes(g.n)), 256), dtype=torch.uint8, device=dev)
+    off = torch.empty(g.n + 1, dtype=torch.int32, device=dev)
+    nid = torch.empty(g.n, dtype=torch.int32, device=dev)
+    cols = torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+    w = None if g.weights is None else torch.empty(max(g.m, 1), dtype=torch.int32, device=dev)
+    _check(lib.lbg_order_graph(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, _ptr(off), _ptr(cols),
+                               _ptr(w), _ptr(nid), _ptr(scratch), scratch.numel(), _stream(stream)))
+    return OrderedGraph(off, cols, w, nid, g.n, g.m)
+
+
 def split_workspace_bytes(n: int, m: int, children: int, sssp: bool = False) -> int:
     return int(lib.lbg_split_workspace_bytes(n, m, children, int(sssp)))
 
@@ -406,14 +444,18 @@ def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None 
 
 def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None = None,
          workspace: Workspace | None = None, stats: bool = False, stream=None, packed: bool = False,
-         mdt: int | None = None):
+         mdt: int | None = None, ordered: bool = False):
     """Distances from ``src`` as an int32 tensor holding uint32 bit patterns
     (use ``.view(torch.uint32)``; UINT32_MAX = unreachable).  ``packed``:
     balanced strategy on the packed arc words (lbg_sssp_packed).  ``mdt``:
-    split size of the 'split' strategy (None: the histogram rule)."""
+    split size of the 'split' strategy (None: the histogram rule).
+    ``ordered``: balanced strategy on the degree-class ordered copy
+    (lbg_sssp_ordered); source and result stay in original ids."""
     s = _strategy(strategy)
-    if packed and s not in (AUTO, BALANCED):
-        raise ValueError("packed arcs run the balanced strategy")
+    if (packed or ordered) and s not in (AUTO, BALANCED):
+        raise ValueError("packed arcs and the ordered copy run the balanced strategy")
+    if packed and ordered:
+        raise ValueError("packed arcs and the ordered copy are separate layouts")
     if g.weights is None:
         raise ValueError("sssp needs weights")
     if out is None:
@@ -422,7 +464,12 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
     st = Stats()
-    if packed:
+    if ordered:
+        og = g.ensure_ordered(stream)
+        rc = lib.lbg_sssp_ordered(_ptr(og.offsets), _ptr(og.cols), _ptr(og.weights), _ptr(og.new_id), g.n, g.m,
+                                  int(src), _ptr(out), _ptr(ws), ws.numel(), ctypes.byref(st) if stats else None,
+                                  _stream(stream))
+    elif packed:
         arcs, wbits = g.ensure_packed(stream)
         rc = lib.lbg_sssp_packed(_ptr(g.offsets), _ptr(arcs), wbits, g.n, g.m, int(src), _ptr(out), _ptr(ws),
                                  ws.numel(), ctypes.byref(st) if stats else None, _stream(stream))

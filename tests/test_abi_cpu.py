@@ -287,3 +287,36 @@ def test_split_scratch_and_argument_errors():
     assert ss(w=None) == lbgmod.EINVAL
     assert ss(cb=None) == lbgmod.EINVAL
     assert ss(wsb=64) == lbgmod.ENOMEM
+
+
+def test_order_scratch_and_argument_errors():
+    al = lambda x: (x + 255) // 256 * 256
+    for n in (1, 4096, 4097, 10**6):
+        nb = (n + 4095) // 4096
+        assert lib.lbg_order_scratch_bytes(n) == al(4 * (32 * nb + 1)) + al(4 * (nb + 1)) + al(4 * n)
+    assert lib.lbg_order_scratch_bytes(0) == 0
+
+    def og(n=10, m=20, offsets=FAKE, cols=FAKE, w=FAKE, oo=FAKE, oc=FAKE, ow=FAKE, nid=FAKE, sc=WS, scb=16):
+        return lib.lbg_order_graph(offsets, cols, w, n, m, oo, oc, ow, nid, sc, scb, None)
+
+    assert og(n=0) == lbgmod.EINVAL
+    assert og(m=-1) == lbgmod.ERANGE
+    assert og(m=2**31) == lbgmod.ERANGE
+    assert og(offsets=None) == lbgmod.EINVAL
+    assert og(oo=None) == lbgmod.EINVAL
+    assert og(nid=None) == lbgmod.EINVAL
+    assert og(cols=None) == lbgmod.EINVAL
+    assert og(oc=None) == lbgmod.EINVAL
+    assert og(ow=None) == lbgmod.EINVAL     # weights without order_weights
+    assert og(w=None) == lbgmod.EINVAL      # order_weights without weights
+    assert og(sc=None) == lbgmod.EINVAL
+    assert og(sc=ctypes.c_void_p(0x10010)) == lbgmod.EINVAL
+    assert og(scb=16) == lbgmod.ENOMEM      # every other argument is valid: fails on the size
+
+    so = lambda n=10, m=20, src=0, nid=FAKE, w=FAKE, wsb=1 << 40: \
+        lib.lbg_sssp_ordered(FAKE, FAKE, w, nid, n, m, src, FAKE, WS, wsb, None, None)
+    assert so(nid=None) == lbgmod.EINVAL
+    assert so(w=None) == lbgmod.EINVAL
+    assert so(src=10) == lbgmod.ERANGE
+    assert so(n=0) == lbgmod.EINVAL
+    assert so(wsb=64) == lbgmod.ENOMEM

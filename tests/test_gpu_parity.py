@@ -416,6 +416,75 @@ def test_split_sizes(mdt):
             assert np.array_equal(d, O.dijkstra(g.offsets, g.cols, g.weights, int(s))), (g.name, s, mdt)
 
 
+def _expected_order(g):
+    """The degree-class ordered copy written out with numpy: classes by bit
+    length of the out-degree, largest first, original order within a class;
+    each list stably partitioned by its destinations' classes."""
+    deg = g.degrees.astype(np.int64)
+    cls = np.array([int(d).bit_length() for d in deg], np.int64)
+    order = np.argsort(-cls, kind="stable")
+    new_id = np.empty(g.n, np.int64)
+    new_id[order] = np.arange(g.n)
+    noff = np.concatenate([[0], np.cumsum(deg[order])])
+    off = g.offsets.astype(np.int64)
+    cols, ws = [], []
+    for v in order:
+        c = g.cols[off[v]: off[v + 1]].astype(np.int64)
+        p = np.argsort(-cls[c], kind="stable")
+        cols.append(new_id[c[p]])
+        ws.append(g.weights[off[v]: off[v + 1]][p])
+    cat = lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt)
+    return new_id, noff, cat(cols, np.int64), cat(ws, np.uint32)
+
+
+@pytest.mark.parametrize("which", ["uniform", "rmat", "hub", "tiny", "single"])
+def test_order_graph_layout(which):
+    """lbg_order_graph against the ordered copy built with numpy: new ids,
+    offsets, renamed and partitioned adjacency, weights, exactly."""
+    rng = np.random.default_rng(6)
+    if which == "uniform":
+        g = graphgen.uniform(12)
+    elif which == "rmat":
+        g = graphgen.rmat(14)
+    elif which == "hub":
+        n = 9000                       # more than two workgroups' chunks of nodes
+        src = np.concatenate([np.zeros(7000, np.int64), np.full(300, 4321), rng.integers(0, n, 20000)])
+        dst = rng.integers(0, n, src.size)
+        g = graphgen.from_edges(n, src, dst, rng.integers(1, 9, src.size), "hub")
+    elif which == "tiny":
+        g = graphgen.from_edges(4, [0, 0, 2, 3, 3, 3], [2, 1, 0, 0, 1, 2], [5, 6, 7, 8, 9, 10], "tiny")
+    else:
+        g = graphgen.from_edges(1, [], [], [], "single")
+    dg = _dev(g)
+    og = lbg.order_graph(dg)
+    new_id, noff, cols, ws = _expected_order(g)
+    assert np.array_equal(og.new_id.cpu().numpy().astype(np.int64), new_id)
+    assert np.array_equal(og.offsets.cpu().numpy().astype(np.int64), noff)
+    assert np.array_equal(og.cols.cpu().numpy()[: g.m].astype(np.int64), cols)
+    assert np.array_equal(og.weights.cpu().numpy().view(np.uint32)[: g.m], ws)
+    bg = lbg.DeviceGraph(dg.offsets, dg.cols, None)  # BFS-only graph: no weights in, none out
+    ob = lbg.order_graph(bg)
+    assert ob.weights is None and np.array_equal(ob.cols.cpu().numpy()[: g.m].astype(np.int64), cols)
+
+
+def test_ordered_sssp_matches_oracle():
+    """SSSP on the ordered copy, source and distances in original ids, equals
+    the oracle on the original graph: tiny, degenerate, skewed, grid."""
+    cases = [(gg, [s]) for gg, s in pins.tiny_graphs(count=20, seed=31)]
+    cases += [(graphgen.from_edges(1, [], [], [], "single-node"), [0]),
+              (graphgen.from_edges(5, [1, 2], [2, 3], [4, 5], "isolated-source"), [0, 1]),
+              (graphgen.from_edges(3, [0, 0, 0, 1], [0, 1, 1, 1], [3, 7, 2, 0], "loops-and-dups"), [0]),
+              (pins.path_graph(3000, np.full(2999, 7)), [0, 1500]),
+              (graphgen.rmat(15), None), (graphgen.grid(64), [0, 100]), (graphgen.uniform(13), [0, 77])]
+    for g, srcs in cases:
+        if srcs is None:
+            srcs = graphgen.sources(g, 3, graphgen.FAMILY_RMAT)
+        dg = _dev(g)
+        for s in srcs:
+            got = _gpu_sssp(dg, s, "balanced", ordered=True)
+            assert np.array_equal(got, O.dijkstra(g.offsets, g.cols, g.weights, int(s))), (g.name, s)
+
+
 def test_repeat_runs_identical():
     """Relaxation order differs from run to run; results must not."""
     g = graphgen.rmat(14)
@@ -487,6 +556,18 @@ def test_device_argument_errors_leave_output_untouched():
 def rmat22():
     g = graphgen.rmat(22)
     return g, _dev(g), graphgen.sources(g, 64, graphgen.FAMILY_RMAT)
+
+
+def test_rmat22_full_ordered(rmat22):
+    """The degree-class ordered copy at the benchmark size: full distance
+    vectors against the oracle for two sources."""
+    g, dg, srcs = rmat22
+    og = dg.ensure_ordered()
+    nid = og.new_id.cpu().numpy()
+    assert np.array_equal(np.sort(nid), np.arange(g.n))  # a permutation
+    for s in srcs[:2]:
+        got = lbg.sssp(dg, int(s), ordered=True).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, O.dijkstra(g.offsets, g.cols, g.weights, int(s)))
 
 
 def test_rmat22_full_packed(rmat22):
