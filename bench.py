@@ -83,6 +83,14 @@ def make_workload(name):
     return g, srcs, desc, sym
 
 
+# Sources whose text decides the expansion kernels' memory traffic: the
+# kernels, the host code that launches them and the ordered-copy builder
+# (the SSSP layout the benchmark times).
+TRAFFIC_SOURCES = ("paper_1711_00231_amd/csrc/lbg_kernels.hpp", "paper_1711_00231_amd/csrc/lbg_device.hpp",
+                   "paper_1711_00231_amd/csrc/lbg_sliced.hpp", "paper_1711_00231_amd/csrc/lbg_order.hpp",
+                   "paper_1711_00231_amd/csrc/lbg.hip")
+
+
 def recorded_traffic():
     """HBM-side bytes per launch of the expansion kernels, from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary; empty when the kernel sources
@@ -91,8 +99,7 @@ def recorded_traffic():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("paper_1711_00231_amd/csrc/lbg_kernels.hpp", "paper_1711_00231_amd/csrc/lbg_device.hpp",
-              "paper_1711_00231_amd/csrc/lbg_sliced.hpp", "paper_1711_00231_amd/csrc/lbg.hip"):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     out = {}
@@ -149,6 +156,17 @@ def run_plain(args, lbg, torch, dev):
     lv_out = torch.empty(g.n, dtype=torch.int32, device=dev)
     d_out = torch.empty(g.n, dtype=torch.int32, device=dev)
     deg = torch.from_numpy(g.degrees).to(dev)
+    # SSSP on the degree-class ordered copy (balanced strategy): built once
+    # per graph before timing, like the CSR itself
+    ordered = args.sssp_layout == "ordered" and args.strategy in ("balanced", "auto")
+    order_ms = None
+    if ordered:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dg.ensure_ordered()
+        torch.cuda.synchronize()
+        order_ms = (time.perf_counter() - t) * 1e3
+        log(f"degree-class ordered copy built in {order_ms:.1f} ms")
 
     # arcs leaving the reached set, per source (a count, not an expected value)
     reach_arcs = {}
@@ -167,7 +185,7 @@ def run_plain(args, lbg, torch, dev):
             t = time.perf_counter()
             lbg.bfs(dg, s, strategy=args.strategy, out=lv_out, workspace=ws)
             t1 = time.perf_counter()
-            lbg.sssp(dg, s, strategy=args.strategy, out=d_out, workspace=ws)
+            lbg.sssp(dg, s, strategy=args.strategy, out=d_out, workspace=ws, ordered=ordered)
             t2 = time.perf_counter()
             if lat is not None:
                 lat["bfs"].append((t1 - t) * 1e3)
@@ -217,6 +235,7 @@ def run_plain(args, lbg, torch, dev):
         "config": {"workload": desc, "graph": g.name, "n": g.n, "m": g.m,
                    "sources_per_step": per, "strategy": args.strategy,
                    **({"slice_min": lbg.get_slice_min()} if args.strategy == "sliced" else {}),
+                   "sssp_layout": "degree-class ordered copy" if ordered else "csr",
                    "solves_timed": 2 * n_solves},
         "bfs_gteps": round(bfs_arcs / (bfs_ms / 1e3) / 1e9, 4),
         "sssp_gteps": round(bfs_arcs / (sssp_ms / 1e3) / 1e9, 4),
@@ -226,13 +245,18 @@ def run_plain(args, lbg, torch, dev):
         "sssp_ms_p50": round(float(np.percentile(lat["sssp"], 50)), 4),
         "sssp_ms_p99": round(float(np.percentile(lat["sssp"], 99)), 4),
     }
+    if order_ms is not None:
+        out["order_build_ms"] = round(order_ms, 3)
     if not args.no_profile:
         kern = {}
         for kind in ("bfs", "sssp"):
             p = prof[kind]
             nl = p["launches"] + p["empty_launches"]
             kname = "balanced" if args.strategy == "auto" else args.strategy
-            kern[kind] = {"kernel": f"k_expand_{kname}<{'true' if kind == 'sssp' else 'false'}>",
+            label = f"k_expand_{kname}<{'true' if kind == 'sssp' else 'false'}>"
+            if kind == "sssp" and ordered:
+                label += " ordered"
+            kern[kind] = {"kernel": label,
                           "launches": nl, "kernel_ms": p["kernel_ms"] + p["empty_ms"],
                           "bytes": algorithmic_bytes(kind, p)}
         dom = max(kern, key=lambda k: kern[k]["kernel_ms"])
@@ -293,25 +317,31 @@ def run_strategies(lbg, torch, g, srcs, dev):
             res[f"{kind}_gteps"] = round(arcs / sum(ts) / 1e9, 3)
         out[strat] = res
         log(f"strategy {strat}: {res}")
+
+    def sssp_layout(name, **kw):
+        ts, arcs = [], 0
+        for s in srcs[:2]:
+            lv = lbg.bfs(dg, int(s), strategy="balanced", workspace=ws).cpu().numpy()
+            arcs += int(deg[lv != lbg.BFS_INF].sum())
+            lbg.sssp(dg, int(s), workspace=ws, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lbg.sssp(dg, int(s), workspace=ws, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        out[name] = {"sssp_ms": [round(x * 1e3, 3) for x in ts], "sssp_gteps": round(arcs / sum(ts) / 1e9, 3)}
+        log(f"strategy {name}: {out[name]}")
+
     # balanced SSSP on packed 32-bit arcs (one load per arc), when ids and
-    # weights fit in 32 bits
+    # weights fit in 32 bits, and on the degree-class ordered copy
     try:
         dg.ensure_packed()
+        sssp_layout("balanced_packed", packed=True)
+        out["balanced_packed"]["wbits"] = dg.packed[1]
     except lbg.LbgError:
-        return out
-    ts, arcs = [], 0
-    for s in srcs[:2]:
-        lv = lbg.bfs(dg, int(s), strategy="balanced", workspace=ws).cpu().numpy()
-        arcs += int(deg[lv != lbg.BFS_INF].sum())
-        lbg.sssp(dg, int(s), workspace=ws, packed=True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        lbg.sssp(dg, int(s), workspace=ws, packed=True)
-        torch.cuda.synchronize()
-        ts.append(time.perf_counter() - t)
-    out["balanced_packed"] = {"wbits": dg.packed[1], "sssp_ms": [round(x * 1e3, 3) for x in ts],
-                              "sssp_gteps": round(arcs / sum(ts) / 1e9, 3)}
-    log(f"strategy balanced_packed: {out['balanced_packed']}")
+        pass
+    dg.ensure_ordered()
+    sssp_layout("balanced_ordered", ordered=True)
     return out
 
 
@@ -502,6 +532,8 @@ def main():
     ap.add_argument("--slice-min", type=int, default=None,
                     help="split degree of the sliced strategy (lbg_set_slice_min)")
     ap.add_argument("--sources-per-step", type=int, default=8)
+    ap.add_argument("--sssp-layout", default="ordered", choices=["csr", "ordered"],
+                    help="SSSP on the input CSR or on its degree-class ordered copy (balanced strategy)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the cpu_baseline leg (0 = skip)")
     ap.add_argument("--no-profile", action="store_true",

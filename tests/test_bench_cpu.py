@@ -14,8 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-SOURCES = ("paper_1711_00231_amd/csrc/lbg_kernels.hpp", "paper_1711_00231_amd/csrc/lbg_device.hpp",
-           "paper_1711_00231_amd/csrc/lbg_sliced.hpp", "paper_1711_00231_amd/csrc/lbg.hip")
+SOURCES = bench.TRAFFIC_SOURCES
 
 
 def test_more_than_one_gpu_is_refused():
