@@ -620,6 +620,9 @@ def test_workspace_reuse_across_sources(strat):
         assert np.array_equal(lv, O.bfs(g.offsets, g.cols, s)), f"bfs src={s}"
         d = lbg.sssp(dg, s, strategy=strat, workspace=ws).cpu().numpy().view(np.uint32)
         assert np.array_equal(d, O.dijkstra(g.offsets, g.cols, g.weights, s)), f"sssp src={s}"
+        if strat == "balanced":  # the ordered copy shares the balanced workspace
+            d = lbg.sssp(dg, s, workspace=ws, ordered=True).cpu().numpy().view(np.uint32)
+            assert np.array_equal(d, O.dijkstra(g.offsets, g.cols, g.weights, s)), f"ordered src={s}"
 
 
 def test_concurrent_solves_on_two_streams():
