@@ -293,8 +293,9 @@ int lbg_sssp_split(const int32_t* split_offsets, const int32_t* child_base, cons
  *     by input position within a class (ascending new id when the input
  *     adjacency lists are sorted).
  * weights and order_weights are both NULL or both given (when m > 0).
- * scratch: device buffer of lbg_order_scratch_bytes(n) bytes (about 4n +
- * 32 bytes per 32 nodes), 256-byte aligned, overwritten.  Outputs are device
+ * scratch: device buffer of lbg_order_scratch_bytes(n) bytes (4n plus 132
+ * bytes per 4096 nodes, each part rounded up to 256), 256-byte aligned,
+ * overwritten.  Outputs are device
  * buffers the caller allocates, not overlapping the inputs; offsets outside
  * [0, m] are clamped and destinations outside [0, n) are copied unchanged
  * (lbg_validate_csr first on untrusted input).  Returns when the outputs are
