@@ -627,10 +627,30 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
       }
     }
     if (__any(bad) && lane == 0) atomicOr(&a.ctl->error, kErrBadArc);
+    // Single solves push in groups of four rounds (at most 256 nodes, the
+    // wave queue's size); a group that would not fit flushes the queue
+    // first, so a push-heavy tile pays one reservation per 256 nodes.
+    // Batched tiles (four rounds in all) push directly.
+    constexpr int kGroup = kMulti ? kItems : 4;
+    static_assert(kItems % kGroup == 0 && 64 * kGroup <= kWQ, "push group must fit the wave queue");
 #pragma unroll
-    for (int r = 0; r < kItems; ++r)
-      wq_push<kPay, T, kNarrow, kSplit>(a, w.qv, w.qq, qcount, push[r], vv[r], kMulti ? qd[kMulti ? r : 0] : 0,
-                                        nxt, nctr);
+    for (int r0 = 0; r0 < kItems; r0 += kGroup) {
+      if constexpr (!kMulti) {
+        uint32_t P = 0;
+#pragma unroll
+        for (int r = r0; r < r0 + kGroup; ++r) P += static_cast<uint32_t>(__popcll(__ballot(push[r])));
+        if (qcount + P > static_cast<uint32_t>(kWQ)) {
+          WaveFlush<kPay, T, kNarrow, kSplit> f;
+          f.flush(a, w.qv, w.qq, qcount, nxt, nctr);
+          qcount = 0;
+          wave_sync();
+        }
+      }
+#pragma unroll
+      for (int r = r0; r < r0 + kGroup; ++r)
+        wq_push<kPay, T, kNarrow, kSplit>(a, w.qv, w.qq, qcount, push[r], vv[r], kMulti ? qd[kMulti ? r : 0] : 0,
+                                          nxt, nctr);
+    }
     if (qcount >= kWQ / 2) {
       WaveFlush<kPay, T, kNarrow, kSplit> f;
       f.flush(a, w.qv, w.qq, qcount, nxt, nctr);
