@@ -651,7 +651,8 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
         wq_push<kPay, T, kNarrow, kSplit>(a, w.qv, w.qq, qcount, push[r], vv[r], kMulti ? qd[kMulti ? r : 0] : 0,
                                           nxt, nctr);
     }
-    if (qcount >= kWQ / 2) {
+    // (single solves flush only when the next group would not fit)
+    if (kMulti && qcount >= kWQ / 2) {
       WaveFlush<kPay, T, kNarrow, kSplit> f;
       f.flush(a, w.qv, w.qq, qcount, nxt, nctr);
       qcount = 0;
