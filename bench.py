@@ -454,14 +454,24 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
     ws1 = lbg.Workspace(dev)
     probe = serve.poisson_requests(1.0, 60, inst, upload_graphs=uploads, upload_share=0.25,
                                    seed=11, sources=srcs)
+    def plain_call(r):
+        """One plain solve of request r: resident instances run SSSP on their
+        degree-class ordered copy, as the plain lane does; uploads use the CSR."""
+        if r.kind == serve.KIND_BFS:
+            lbg.bfs(singles[r.instance] if r.instance else up_dev[id(r.graph)], r.src, workspace=ws1)
+        elif r.instance:
+            lbg.sssp(singles[r.instance], r.src, workspace=ws1, ordered=True)
+        else:
+            lbg.sssp(up_dev[id(r.graph)], r.src, workspace=ws1)
+
+    for gd in singles.values():
+        gd.ensure_ordered()
     svc = []
     for r in probe:
-        gd = singles[r.instance] if r.instance else up_dev[id(r.graph)]
-        f = lbg.bfs if r.kind == serve.KIND_BFS else lbg.sssp
-        f(gd, r.src, workspace=ws1)
+        plain_call(r)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        f(gd, r.src, workspace=ws1)
+        plain_call(r)
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t)
     sat = 1.0 / float(np.mean(svc))
@@ -470,7 +480,7 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
                      max_level_arcs=min(2**32 - 1, 8 * (u.m + R * MC)))
     # the plain lane holds every resident instance: large ones always go
     # there, small ones only when the engine and the lane are both idle
-    lane = serve.gpu_plain_lane(singles, big_arcs)
+    lane = serve.gpu_plain_lane(singles, big_arcs, ordered_sssp=True)
 
     def plain_serve(reqs):
         """The same arrivals served FCFS by one plain call per request (upload
@@ -480,9 +490,7 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         for r in reqs:
             while time.perf_counter() - t0 < r.arrival:
                 pass
-            gd = singles[r.instance] if r.instance else up_dev[id(r.graph)]
-            f = lbg.bfs if r.kind == serve.KIND_BFS else lbg.sssp
-            f(gd, r.src, workspace=ws1)
+            plain_call(r)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - t0 - r.arrival)
         wall = time.perf_counter() - t0
@@ -516,7 +524,8 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
                         f"{requests_per_point} requests per point; gteps counts instance arcs; "
                         f"instances of >= {big_arcs} arcs are served by plain solves on a second "
                         f"stream, the rest are batched unless the engine and that stream are both "
-                        f"idle (then a resident query runs plain: 'bypassed'); the engine advances "
+                        f"idle (then a resident query runs plain: 'bypassed'); plain solves of "
+                        f"resident instances run SSSP on their degree-class ordered copy; the engine advances "
                         f"2 levels per step; plain_* = the same "
                         f"arrivals served FCFS by one plain call each"}
 

@@ -490,11 +490,12 @@ class UploadArena:
         return lo, lo + g.n, g.m
 
 
-def gpu_plain_lane(graphs: dict, big_arcs: int) -> PlainLane:
+def gpu_plain_lane(graphs: dict, big_arcs: int, ordered_sssp: bool = False) -> PlainLane:
     """A PlainLane over resident device graphs (instance name -> DeviceGraph
     with local node ids): each query runs as one balanced BFS/SSSP solve on
     a stream of its own.  Instances below big_arcs given here are served by
-    the lane only through a server's idle bypass."""
+    the lane only through a server's idle bypass.  ordered_sssp: SSSP runs
+    on each graph's degree-class ordered copy (built here, once)."""
     import torch
 
     from . import lbg
@@ -506,11 +507,16 @@ def gpu_plain_lane(graphs: dict, big_arcs: int) -> PlainLane:
     ws.get(max(max(lbg.workspace_bytes(g.n, g.m, "balanced", False),
                    lbg.workspace_bytes(g.n, g.m, "balanced", True)) for g in gs))
     out = torch.empty(max(g.n for g in gs), dtype=torch.int32, device=dev)
+    if ordered_sssp:
+        for g in gs:
+            g.ensure_ordered()
 
     def solve(r, keep):
         g = graphs[r.instance]
-        f = lbg.bfs if r.kind == KIND_BFS else lbg.sssp
-        f(g, r.src, out=out[: g.n], workspace=ws, stream=stream)
+        if r.kind == KIND_BFS:
+            lbg.bfs(g, r.src, out=out[: g.n], workspace=ws, stream=stream)
+        else:
+            lbg.sssp(g, r.src, out=out[: g.n], workspace=ws, stream=stream, ordered=ordered_sssp)
         if not keep:
             return None
         with torch.cuda.stream(stream):

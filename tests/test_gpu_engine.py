@@ -106,12 +106,13 @@ def test_server_loop_on_gpu_with_uploads():
         g = gs[int(r.instance[1:])] if r.instance is not None else r.graph
         assert np.array_equal(r.result, _expected(g, r.src, r.kind)), r.rid
     # idle bypass on wall-clock arrivals: the lane holds every resident
-    # instance, and a small query that finds the engine and the lane idle is
-    # solved plain; its result still matches the oracle
+    # instance (SSSP on their ordered copies), and a small query that finds
+    # the engine and the lane idle is solved plain; its result still matches
+    # the oracle
     lane = serve.gpu_plain_lane({nm: lbg.DeviceGraph.from_numpy(gs[int(nm[1:])].offsets,
                                                                 gs[int(nm[1:])].cols,
                                                                 gs[int(nm[1:])].weights)
-                                 for nm in inst}, big_arcs=inst[big].arcs)
+                                 for nm in inst}, big_arcs=inst[big].arcs, ordered_sssp=True)
     reqs = serve.poisson_requests(300.0, 30, inst, upload_graphs=uploads, upload_share=0.3, seed=9)
     rep = serve.Server(eng, inst, upload=arena, keep_results=True, plain=lane, idle_bypass=True).run(reqs)
     assert len(rep.completed) == 30
