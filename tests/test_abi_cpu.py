@@ -320,3 +320,21 @@ def test_order_scratch_and_argument_errors():
     assert so(src=10) == lbgmod.ERANGE
     assert so(n=0) == lbgmod.EINVAL
     assert so(wsb=64) == lbgmod.ENOMEM
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/lbg.h is a C header: it compiles as strict C99 with no
+    warnings (no C++ or torch types in the boundary)."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "h.c"
+    src.write_text('#include "lbg.h"\nint main(void) { return (int)sizeof(lbg_stats) == 40 ? 0 : 1; }\n')
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), "-o", str(tmp_path / "h"), str(src)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert subprocess.run([str(tmp_path / "h")], timeout=60).returncode == 0
