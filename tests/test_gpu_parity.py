@@ -385,6 +385,26 @@ def test_split_graph_layout(which, mdt):
     assert sb.weights is None and np.array_equal(sb.cols.cpu().numpy()[: g.m], g.cols[order])
 
 
+def test_split_graph_rejects_wrong_child_count():
+    """lbg_split_graph recounts the children on the device and refuses a
+    caller's count that differs (the output arrays would be mis-sized)."""
+    import ctypes
+
+    g = graphgen.rmat(11)
+    dg = _dev(g)
+    c = lbg.split_count(dg, 8)
+    assert c > 0
+    so = torch.empty(g.n + c + 1, dtype=torch.int32, device="cuda")
+    cb = torch.empty(g.n + 1, dtype=torch.int32, device="cuda")
+    cols = torch.empty(g.m, dtype=torch.int32, device="cuda")
+    scratch = torch.empty(max(int(lbg.lib.lbg_split_scratch_bytes(g.n)), 256), dtype=torch.uint8, device="cuda")
+    for wrong in (c - 1, c + 1):
+        rc = lbg.lib.lbg_split_graph(lbg._ptr(dg.offsets), lbg._ptr(dg.cols), None, g.n, g.m, 8, wrong,
+                                     lbg._ptr(so), lbg._ptr(cb), lbg._ptr(cols), None, lbg._ptr(scratch),
+                                     scratch.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == lbg.EINVAL and "child" in lbg.lib.lbg_last_error().decode()
+
+
 @pytest.mark.parametrize("mdt", [1, 2, 7, 64, 5000])
 def test_split_sizes(mdt):
     """Node splitting at split sizes from every arc its own child (1) to no
