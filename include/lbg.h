@@ -48,10 +48,11 @@
  *   LBG_SPLIT     node splitting with child nodes (Section III-B): a node
  *                 with more than MDT out-arcs is cut into ceil(deg / MDT)
  *                 pieces; it keeps the first, and child nodes of a split
- *                 graph built once (lbg_split_graph) hold the others; a pushed node queues
- *                 its own piece and its children's, which carry its distance
- *                 (the parent-to-child propagation), and the pieces are tiled
- *                 as in LBG_BALANCED (lbg_bfs_split, lbg_sssp_split)
+ *                 graph built once (lbg_split_graph) hold the others.  A
+ *                 pushed node queues its own piece and its children's, which
+ *                 carry its distance (the parent-to-child propagation), and
+ *                 the pieces are tiled as in LBG_BALANCED (lbg_bfs_split,
+ *                 lbg_sssp_split)
  *   LBG_AUTO      currently LBG_BALANCED
  *
  * Conventions for every entry point
