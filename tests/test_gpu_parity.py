@@ -514,6 +514,8 @@ def test_repeat_runs_identical():
     for strat in STRATS:
         for _ in range(5):
             assert np.array_equal(_gpu_sssp(dg, s, strat), exp)
+    for _ in range(5):
+        assert np.array_equal(_gpu_sssp(dg, s, "balanced", ordered=True), exp)
 
 
 def test_stats_and_validate():
