@@ -363,7 +363,7 @@ def test_idle_bypass_on_spaced_arrivals_and_names():
     gs, u, inst = _setup()
     lane = serve.PlainLane(_oracle_solve(gs), big_arcs=1 << 40, names=["g0", "g2"])
     eng = FakeEngine(u, max_queries=4, max_rows=12000)
-    reqs = [serve.Request(i, 0.03 * i, serve.KIND_BFS if i % 2 else serve.KIND_SSSP, f"g{i % 3}", 5 + i)
+    reqs = [serve.Request(i, 0.1 * i, serve.KIND_BFS if i % 2 else serve.KIND_SSSP, f"g{i % 3}", 5 + i)
             for i in range(9)]
     rep = serve.Server(eng, inst, keep_results=True, plain=lane, idle_bypass=True).run(reqs)
     assert len(rep.completed) == 9
