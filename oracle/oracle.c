@@ -416,7 +416,11 @@ int oracle_hp_schedule(int64_t count, const int64_t* deg, int64_t mdt,
        whose edges were not exhausted by the first s windows */
     int64_t size = 0;
     for (int64_t k = 0; k < count; ++k)
+#if ORACLE_MUTANT == 8
+      if (s == 0 || deg[k] >= s * mdt) size++; /* planted: a node whose edges end exactly on a window boundary stays one sub-iteration too long */
+#else
       if (s == 0 || deg[k] > s * mdt) size++;
+#endif
     if (size == 0) break;
     if (sizes_out && s < max_sub) sizes_out[s] = size;
     ++s;

@@ -242,6 +242,9 @@ def pin_paper_examples(O):
     sizes = O.hp_schedule([int(x) for x in kv["degrees"]], int(kv["mdt"][0]))
     if list(sizes) != [int(x) for x in kv["sublist_sizes"]]:
         fails.append(f"HP schedule: got {list(sizes)}")
+    one = O.hp_schedule([int(kv["single_degree"][0])], int(kv["single_mdt"][0]))
+    if list(one) != [1] * int(kv["single_subiterations"][0]):
+        fails.append(f"HP schedule of one node with {kv['single_degree'][0]} edges: got {list(one)}")
     kv = {r[0]: r[1:] for r in _read_kv("ns_example.txt")}
     pieces = O.ns_pieces(int(kv["degree"][0]), int(kv["mdt"][0]))
     if list(pieces) != [int(x) for x in kv["pieces"]]:

@@ -24,6 +24,7 @@ MUTANTS = {
     5: "certificate skips the tight-arc reachability check",
     6: "MDT with a 0-based bin index",
     7: "WD split with floor instead of ceil",
+    8: "HP sublist keeps a node whose edges end on a window boundary",
 }
 
 
