@@ -116,10 +116,17 @@ typedef enum {
  *         SSSP: Bellman-Ford iterations).
  * frontier_entries: total worklist entries processed (nodes; LBG_EDGE: edges;
  *         LBG_SLICED: (node, slice) pairs; LBG_SPLIT: pieces).
- * edges_scanned: total arcs relaxed (BFS: the arcs leaving reached nodes;
- *         SSSP: at least that, re-relaxations included).
+ * edges_scanned: total arcs of the worklist entries processed (BFS: the
+ *         arcs leaving reached nodes; SSSP: at least that, re-relaxations
+ *         included).
  * updates: successful distance improvements (SSSP) or discoveries (BFS).
- * atomics: device-scope atomics issued on node state (claims / atomicMin). */
+ * atomics: device-scope atomics issued on node state (claims / atomicMin).
+ * edges_skipped: the part of edges_scanned that was never loaded: the arcs
+ *         of SSSP worklist entries whose node improved again during the
+ *         iteration that expands them (the node is queued for the next
+ *         iteration, where its arcs are relaxed with the better distance).
+ *         edges_scanned - edges_skipped arcs were read and relaxed.  0 for
+ *         BFS and for strategies that relax every queued arc. */
 typedef struct {
   int32_t levels;
   int32_t reserved;
@@ -127,6 +134,7 @@ typedef struct {
   int64_t edges_scanned;
   int64_t updates;
   int64_t atomics;
+  int64_t edges_skipped;
 } lbg_stats;
 
 /* Bytes of device workspace a bfs (is_sssp = 0) or sssp (is_sssp = 1) call
@@ -155,6 +163,15 @@ int lbg_bfs(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, i
 int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
              int64_t m, int32_t src, uint32_t* dist_out, void* workspace, size_t workspace_bytes,
              int32_t strategy, const int32_t* coo_src, lbg_stats* stats, void* stream);
+
+/* COO source array of a CSR graph (what LBG_EDGE and LBG_EDGE_NOCHUNK
+ * read beside the CSR; Section II-B): coo_out[e] = the node u with
+ * offsets[u] <= e < offsets[u + 1], for every arc e in [0, m).  coo_out is a
+ * device int32[m] the caller allocates (may be NULL when m = 0).  Offsets
+ * outside [0, m] are clamped (lbg_validate_csr first on untrusted input).
+ * Returns after coo_out is written; LBG_EINVAL / LBG_ERANGE on bad
+ * arguments. */
+int lbg_coo_sources(const int32_t* offsets, int32_t n, int64_t m, int32_t* coo_out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Packed arcs for SSSP (the balanced strategy of Section III-A on a denser
@@ -323,6 +340,29 @@ int lbg_validate_csr(const int32_t* offsets, const int32_t* cols, int32_t n, int
                      void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Hierarchical processing (LBG_HIER, Section III-C).
+ *
+ * lbg_set_hier_mdt: process-wide MDT of LBG_HIER solves that start later; 0
+ * (the default) = the histogram rule of Section III-B per solve (as
+ * lbg_degree_mdt), > 0 = that window length.  LBG_EINVAL if negative.
+ * lbg_get_hier_mdt returns the setting.
+ *
+ * lbg_hier_last_schedule: the sub-iteration schedule of the calling thread's
+ * last LBG_HIER solve: sizes[l * max_subs + s] (host array of max_levels *
+ * max_subs int32) = the number of worklist entries active in sub-iteration s
+ * of level l (sub-iteration 0 holds the whole worklist; an entry stays active
+ * while it has arcs beyond the windows already processed), 0 past the last
+ * sub-iteration.  The sub-iteration whose sublist holds fewer than 1024
+ * entries expands all of their remaining arcs (the hand-over to workload
+ * decomposition), so it is the level's last.  Recorded for levels < 64 and
+ * sub-iterations < 256.  Returns the number of levels written (at most
+ * max_levels; 0 before any LBG_HIER solve); *mdt_out (nullable) receives the
+ * MDT that solve used. */
+int lbg_set_hier_mdt(int32_t mdt);
+int32_t lbg_get_hier_mdt(void);
+int32_t lbg_hier_last_schedule(int32_t* sizes, int32_t max_levels, int32_t max_subs, int32_t* mdt_out);
+
+/* ------------------------------------------------------------------------
  * Degree-bin parameters of LBG_BINNED solves (process-wide).
  *   mdt      split size: a node with more out-arcs is queued as ceil(deg/mdt)
  *            pieces, the first deg % pieces of them one arc longer (0 = no
@@ -380,6 +420,7 @@ typedef struct {
   int64_t edges_scanned;     /* arcs they relaxed */
   int64_t updates;           /* successful distance improvements/discoveries */
   int64_t atomics;           /* device-scope atomics issued on node state */
+  int64_t edges_skipped;     /* arcs of edges_scanned never loaded (lbg_stats) */
 } lbg_profile;
 
 /* Totals since the last reset of the one-level launches of BFS solves

@@ -39,6 +39,21 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(LBG_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Names of the device guard flags set in Ctl::error.
+const char* guard_names(unsigned flags) {
+  thread_local char buf[160];
+  buf[0] = 0;
+  static const char* names[] = {"worklist capacity", "tile-mark capacity", "edge-worklist capacity",
+                                "arc outside the graph", "tile without an entry", "source outside [0, n)",
+                                "malformed split table"};
+  for (int b = 0; b < 7; ++b)
+    if (flags & (1u << b)) {
+      if (buf[0]) strncat(buf, ", ", sizeof(buf) - strlen(buf) - 1);
+      strncat(buf, names[b], sizeof(buf) - strlen(buf) - 1);
+    }
+  return buf;
+}
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -48,7 +63,8 @@ int32_t resolve(int32_t s) { return s == LBG_AUTO ? LBG_BALANCED : s; }
 
 // Workspace layout.  All offsets 256-byte aligned.
 struct Layout {
-  size_t ctl, visited, seen[2], xfilter, dstate, d16, node[2], eprefix[2], estart[2], tile[2], sub[2], total;
+  size_t ctl, visited, seen[2], xfilter, dstate, d16, node[2], eprefix[2], estart[2], tile[2], sub[2],
+      hier_trace, total;
   uint32_t node_cap, tile_cap, edge_cap;
 };
 
@@ -105,6 +121,7 @@ Layout layout(int32_t n, int64_t m, int32_t strategy, int is_sssp, int64_t child
       L.tile[b] = take(sizeof(int32_t) * static_cast<size_t>(L.tile_cap));
       if (s == LBG_HIER) L.sub[b] = take(sizeof(int32_t) * static_cast<size_t>(n));
     }
+    if (s == LBG_HIER) L.hier_trace = take(sizeof(uint32_t) * lbg::kHierTraceLevels * lbg::kHierTraceSubs);
   }
   L.total = off;
   return L;
@@ -217,6 +234,12 @@ int grid_blocks() { return grids().bal[0][1]; }
 std::mutex g_bins_mu;
 lbg_bins g_bins{256, 16, 1024};  // what the autotuner picks on R-MAT scale 22
 int32_t g_slice_min = 512;       // LBG_SLICED: degree from which a node is split by slice
+int32_t g_hier_mdt = 0;          // LBG_HIER: fixed MDT (0 = the histogram rule per solve)
+
+// Sub-iteration schedule of this thread's last LBG_HIER solve (read back
+// from the workspace after the solve): sublist sizes, kHierTraceSubs per level.
+thread_local std::vector<uint32_t> g_hier_sched;
+thread_local int32_t g_hier_sched_levels = 0, g_hier_sched_mdt = 0;
 
 // Host side of the profiling counters (see lbg_profile_enable).
 std::mutex g_prof_mu;
@@ -373,6 +396,7 @@ int solve(const Problem& P) {
     }
     if (strat == LBG_HIER) a.sub[b] = reinterpret_cast<int32_t*>(ws + Lay.sub[b]);
   }
+  if (strat == LBG_HIER) a.hier_trace = reinterpret_cast<uint32_t*>(ws + Lay.hier_trace);
   a.ctl = reinterpret_cast<Ctl*>(ws + Lay.ctl);
   a.n = static_cast<uint32_t>(P.n);
   a.m = static_cast<uint32_t>(P.m);
@@ -431,7 +455,12 @@ int solve(const Problem& P) {
     HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const uint32_t mx = host->deg_max;
-    hier_mdt = mdt_rule(host);
+    int32_t fixed;
+    {
+      std::lock_guard<std::mutex> lk(g_bins_mu);
+      fixed = g_hier_mdt;
+    }
+    hier_mdt = fixed > 0 ? static_cast<uint32_t>(fixed) : mdt_rule(host);
     hier_subs = std::max<uint32_t>(1, (mx + hier_mdt - 1) / hier_mdt);
   }
 
@@ -564,7 +593,7 @@ int solve(const Problem& P) {
     HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (host->error)
-      return fail(LBG_EOVERFLOW, "device capacity guard tripped (flags 0x%x)", host->error);
+      return fail(LBG_EOVERFLOW, "device guard tripped (flags 0x%x: %s)", host->error, guard_names(host->error));
     L = host->levels;
     uint64_t ef = static_cast<uint32_t>(host->ctr[L % 3]), nfr = host->ctr[L % 3] >> 32;
     if (sl) {  // the mixed list's tail (ctr) plus the 8 slice tails
@@ -585,6 +614,14 @@ int solve(const Problem& P) {
   }
 
   g_level_hint[P.is_sssp ? 1 : 0] = used_small ? 0u : host->levels;
+  if (strat == LBG_HIER) {
+    g_hier_sched.assign(static_cast<size_t>(lbg::kHierTraceLevels) * lbg::kHierTraceSubs, 0u);
+    HIP_TRY(hipMemcpyAsync(g_hier_sched.data(), a.hier_trace, sizeof(uint32_t) * g_hier_sched.size(),
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    g_hier_sched_levels = static_cast<int32_t>(std::min<uint32_t>(host->levels, lbg::kHierTraceLevels));
+    g_hier_sched_mdt = static_cast<int32_t>(hier_mdt);
+  }
   const int64_t p_upd = xsum(host, 2), p_atom = xsum(host, 3);
   if (profiling) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -611,6 +648,7 @@ int solve(const Problem& P) {
     gp.edges_scanned += static_cast<int64_t>(host->edges_scanned) - pes;
     gp.updates += xsum(host, 0);
     gp.atomics += xsum(host, 1);
+    gp.edges_skipped += xsum(host, 7);
     pp.frontier_entries += pfe;
     pp.edges_scanned += pes;
     pp.updates += p_upd;
@@ -623,6 +661,7 @@ int solve(const Problem& P) {
     P.stats->edges_scanned = static_cast<int64_t>(host->edges_scanned);
     P.stats->updates = xsum(host, 0) + p_upd;
     P.stats->atomics = xsum(host, 1) + p_atom;
+    P.stats->edges_skipped = xsum(host, 7);
   }
   return LBG_OK;
 }
@@ -842,7 +881,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
       HIP_TRY(hipGraphLaunch(exec, st));
       HIP_TRY(hipStreamSynchronize(st));
       if (host->error)
-        return fail(LBG_EOVERFLOW, "device capacity/bounds guard tripped (flags 0x%x)", host->error);
+        return fail(LBG_EOVERFLOW, "device guard tripped (flags 0x%x: %s)", host->error, guard_names(host->error));
       L = host->level_base;
       if (static_cast<uint32_t>(host->ctr[L % 3]) == 0u) break;
       if (L > level_cap) return fail(LBG_EINTERNAL, "more levels than rows; malformed input?");
@@ -871,7 +910,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
     HIP_TRY(hipMemcpyAsync(host, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (host->error)
-      return fail(LBG_EOVERFLOW, "device capacity/bounds guard tripped (flags 0x%x)", host->error);
+      return fail(LBG_EOVERFLOW, "device guard tripped (flags 0x%x: %s)", host->error, guard_names(host->error));
     if (static_cast<uint32_t>(host->ctr[L % 3]) == 0u) break;
     if (L > level_cap) return fail(LBG_EINTERNAL, "more levels than rows; malformed input?");
     batch = std::min<uint32_t>(batch * 2, 64);
@@ -894,6 +933,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
     gp.edges_scanned += static_cast<int64_t>(host->edges_scanned);
     gp.updates += xsum(host, 0);
     gp.atomics += xsum(host, 1);
+    gp.edges_skipped += xsum(host, 7);
   }
   if (stats) {
     stats->levels = static_cast<int32_t>(host->levels);
@@ -902,6 +942,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
     stats->edges_scanned = static_cast<int64_t>(host->edges_scanned);
     stats->updates = xsum(host, 0);
     stats->atomics = xsum(host, 1);
+    stats->edges_skipped = xsum(host, 7);
   }
   return LBG_OK;
 }
@@ -956,7 +997,8 @@ int engine_sync_state(lbg_engine* e) {
                          hipMemcpyDeviceToHost, e->st));
   HIP_TRY(hipStreamSynchronize(e->st));
   if (e->host_ctl->error)
-    return fail(LBG_EOVERFLOW, "device capacity/bounds guard tripped (flags 0x%x)", e->host_ctl->error);
+    return fail(LBG_EOVERFLOW, "device guard tripped (flags 0x%x: %s)", e->host_ctl->error,
+                guard_names(e->host_ctl->error));
   return LBG_OK;
 }
 
@@ -1172,6 +1214,7 @@ int lbg_engine_info(const lbg_engine* e, lbg_stats* stats, int32_t* running, uin
     stats->edges_scanned = static_cast<int64_t>(e->host_ctl->edges_scanned);
     stats->updates = xsum(e->host_ctl, 0);
     stats->atomics = xsum(e->host_ctl, 1);
+    stats->edges_skipped = xsum(e->host_ctl, 7);
   }
   return LBG_OK;
 }
@@ -1234,6 +1277,22 @@ int lbg_slice_graph(const int32_t* offsets, const int32_t* cols, const uint32_t*
   return LBG_OK;
 }
 
+int lbg_coo_sources(const int32_t* offsets, int32_t n, int64_t m, int32_t* coo_out, void* stream) {
+  if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
+  if (m < 0 || m > INT32_MAX)
+    return fail(LBG_ERANGE, "m must be in [0, INT32_MAX] (got %lld)", static_cast<long long>(m));
+  if (!offsets || (m > 0 && !coo_out)) return fail(LBG_EINVAL, "null offsets or output pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (m > 0) {
+    const int blocks = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(n) + lbg::kWaves - 1) / lbg::kWaves, 4096));
+    hipLaunchKernelGGL(lbg::k_coo_sources, dim3(blocks), dim3(lbg::kBlock), 0, st, offsets,
+                       static_cast<uint32_t>(n), static_cast<uint32_t>(m), coo_out);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return LBG_OK;
+}
+
 int lbg_pack_arcs(const int32_t* cols, const uint32_t* weights, int32_t n, int64_t m, uint32_t* arcs_out,
                   int32_t* wbits_out, void* workspace, size_t workspace_bytes, void* stream) {
   if (n <= 0) return fail(LBG_EINVAL, "n must be positive (got %d)", n);
@@ -1280,6 +1339,32 @@ int lbg_sssp_packed(const int32_t* offsets, const uint32_t* arcs, int32_t wbits,
   P.wbits = wbits;
   if (m > 0 && !arcs) return fail(LBG_EINVAL, "null arcs pointer with m > 0");
   return solve(P);
+}
+
+int lbg_set_hier_mdt(int32_t mdt) {
+  if (mdt < 0) return fail(LBG_EINVAL, "MDT must be >= 0 (got %d)", mdt);
+  std::lock_guard<std::mutex> lk(g_bins_mu);
+  g_hier_mdt = mdt;
+  return LBG_OK;
+}
+
+int32_t lbg_get_hier_mdt(void) {
+  std::lock_guard<std::mutex> lk(g_bins_mu);
+  return g_hier_mdt;
+}
+
+int32_t lbg_hier_last_schedule(int32_t* sizes, int32_t max_levels, int32_t max_subs, int32_t* mdt_out) {
+  if (mdt_out) *mdt_out = g_hier_sched_mdt;
+  const int32_t nl = std::min(g_hier_sched_levels, std::max(max_levels, 0));
+  const int32_t ns = std::min<int32_t>(static_cast<int32_t>(lbg::kHierTraceSubs), std::max(max_subs, 0));
+  if (sizes) {
+    for (int64_t k = 0; k < static_cast<int64_t>(std::max(max_levels, 0)) * std::max(max_subs, 0); ++k) sizes[k] = 0;
+    for (int32_t l = 0; l < nl; ++l)
+      for (int32_t k = 0; k < ns; ++k)
+        sizes[static_cast<size_t>(l) * max_subs + k] =
+            static_cast<int32_t>(g_hier_sched[static_cast<size_t>(l) * lbg::kHierTraceSubs + k]);
+  }
+  return nl;
 }
 
 int lbg_set_slice_min(int32_t min_degree) {

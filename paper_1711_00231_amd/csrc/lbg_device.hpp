@@ -139,7 +139,12 @@ struct KArgs {
   // the new id of original node v; the source is given and the distances
   // are written in original ids (null: no renaming).
   const int32_t* node_map;
+  // Hierarchical strategy: sublist size of sub-iteration s of level L at
+  // [L * kHierTraceSubs + s] for L < kHierTraceLevels, s < kHierTraceSubs
+  // (null: not recorded).
+  uint32_t* hier_trace;
 };
+constexpr uint32_t kHierTraceLevels = 64, kHierTraceSubs = 256;
 
 // Pieces of a node with d out-arcs under split size mdt, and piece k's
 // offset within the node's arcs and length: the first d % p pieces carry one
@@ -156,8 +161,12 @@ __device__ __forceinline__ void split_piece(uint32_t d, uint32_t p, uint32_t k, 
 
 // Ctl::error bits.  None can trip for a well-formed CSR; they turn what
 // would otherwise be an out-of-bounds access into an LBG_EOVERFLOW return.
+// kErrBadSrc: the source, after renaming through node_map, is outside
+// [0, n) (a new-id table that does not belong to the graph); kErrBadSplit: a
+// split graph's child table names a child outside the graph or a child piece
+// without arcs (tables that did not come from lbg_split_graph).
 constexpr unsigned kErrNodeCap = 1u, kErrTileCap = 2u, kErrEdgeCap = 4u, kErrBadArc = 8u,
-                   kErrBadTile = 16u;
+                   kErrBadTile = 16u, kErrBadSrc = 32u, kErrBadSplit = 64u;
 
 // Address of element idx of an array.  With kNarrow the byte offset is
 // formed in 32 bits, so the access is a uniform (SGPR) base plus a 32-bit
@@ -422,11 +431,17 @@ __device__ __forceinline__ void write_entry(const KArgs& a, const Frontier& out,
   }
 }
 
-// Split graph: the children of parent v and the arcs they hold in total.
+// Split graph: the children of parent v and the arcs they hold in total.  A
+// child range that is decreasing or leaves the graph's n + C nodes (node_cap
+// = n + C) is flagged and treated as empty.
 __device__ __forceinline__ void split_children(const KArgs& a, int32_t v, int32_t* cb, int32_t* ce,
                                                int32_t* arcs) {
   *cb = a.child_base[v];
   *ce = a.child_base[v + 1];
+  if (*cb < 0 || *ce < *cb || static_cast<uint32_t>(*ce) > a.node_cap - a.n) {
+    atomicOr(&a.ctl->error, kErrBadSplit);
+    *ce = *cb = 0;
+  }
   *arcs = *ce > *cb ? a.offsets[a.n + *ce] - a.offsets[a.n + *cb] : 0;
 }
 
@@ -446,7 +461,12 @@ __device__ __forceinline__ void write_split_entries(const KArgs& a, const Fronti
   for (int32_t c = cb; c < ce; ++c) {
     const int32_t cs = a.offsets[a.n + c];
     const int32_t cl = a.offsets[a.n + c + 1] - cs;
-    if (cl <= 0) continue;
+    if (cl <= 0) {
+      // the reservation counted this piece: its slot stays unwritten, so the
+      // solve must not be trusted (lbg_split_graph never writes such pieces)
+      atomicOr(&a.ctl->error, kErrBadSplit);
+      continue;
+    }
     write_entry<kPay, kTileE, kNarrow>(a, out, i, p, v, q, cs, cl);
     ++i;
     p += static_cast<uint32_t>(cl);

@@ -106,25 +106,31 @@ __device__ __forceinline__ void refresh_seen(const KArgs& a, uint32_t L) {
 
 // Block-level reduction of the per-thread counters, then one atomic per
 // block on this XCD's stats line.  Must be reached by the whole block.
-__device__ __forceinline__ void add_stats(const KArgs& a, uint32_t upd, uint32_t atom) {
+// skip: arcs of worklist entries passed over without loading them (an SSSP
+// node that improved again in the iteration that expands it; its arcs are
+// relaxed in the next one), kept in slot 7.
+__device__ __forceinline__ void add_stats(const KArgs& a, uint32_t upd, uint32_t atom, uint32_t skip = 0u) {
   if (!a.count_stats) return;  // kernel-argument uniform
-  __shared__ uint32_t red[2][kWaves];
-  const uint32_t su = wave_sum(upd), sa = wave_sum(atom);
+  __shared__ uint32_t red[3][kWaves];
+  const uint32_t su = wave_sum(upd), sa = wave_sum(atom), sk = wave_sum(skip);
   const uint32_t wid = threadIdx.x >> 6;
   if (lane_id() == 0) {
     red[0][wid] = su;
     red[1][wid] = sa;
+    red[2][wid] = sk;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long tu = 0, ta = 0;
+    unsigned long long tu = 0, ta = 0, tk = 0;
     for (int w = 0; w < kWaves; ++w) {
       tu += red[0][w];
       ta += red[1][w];
+      tk += red[2][w];
     }
     const int x = blockIdx.x % kXcds;
     if (tu) atomicAdd(&a.ctl->xstat[x][0], tu);
     if (ta) atomicAdd(&a.ctl->xstat[x][1], ta);
+    if (tk) atomicAdd(&a.ctl->xstat[x][7], tk);
   }
 }
 
@@ -209,23 +215,42 @@ __device__ __forceinline__ void init_state(const KArgs& a, int32_t src, uint32_t
 
 template <bool kSssp, bool kEdgeWl>
 __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
-  if (a.node_map) src = a.node_map[src];  // the host checked 0 <= src < n
   const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t stride = gridDim.x * kBlock;
+  // the host checked 0 <= src < n; a renaming table is the caller's array
+  if (a.node_map) src = a.node_map[src];
+  if (static_cast<uint32_t>(src) >= a.n) {
+    if (gid == 0) {
+      a.ctl->error = kErrBadSrc;
+      a.ctl->levels = 0u;
+      a.ctl->ctr[0] = a.ctl->ctr[1] = a.ctl->ctr[2] = 0ull;  // every level finds no work
+    }
+    return;
+  }
   init_state<kSssp>(a, src, gid, stride);
+  if (a.hier_trace)
+    for (uint32_t k = gid; k < kHierTraceLevels * kHierTraceSubs; k += stride) a.hier_trace[k] = 0u;
   const int32_t s0 = a.offsets[src];
-  const int32_t d0 = a.offsets[src + 1] - s0;
+  int32_t d0 = a.offsets[src + 1] - s0;
+  if (s0 < 0 || d0 < 0 || static_cast<uint32_t>(s0) + static_cast<unsigned long long>(d0) > a.m) {
+    if (gid == 0) atomicOr(&a.ctl->error, kErrBadArc);  // malformed offsets: start with no work
+    d0 = 0;
+  }
   if (kEdgeWl) {
     for (uint32_t k = gid; k < static_cast<uint32_t>(d0); k += stride) a.fr[0].node[k] = s0 + k;
   } else {
     constexpr uint32_t T = TileCfg<kSssp>::kEdges;
     const uint32_t tiles = (static_cast<uint32_t>(d0) + T - 1) / T;
-    for (uint32_t t = gid; t < tiles; t += stride) a.fr[0].tile_node[t] = 0;
+    for (uint32_t t = gid; t < tiles && t < a.tile_cap; t += stride) a.fr[0].tile_node[t] = 0;
   }
   if (!kEdgeWl && a.child_base) {
     // split graph: the source's own piece, then its children's pieces (one
     // thread; tile marks by the thread that owns each tile)
-    const int32_t cb = a.child_base[src], ce = a.child_base[src + 1];
+    int32_t cb = a.child_base[src], ce = a.child_base[src + 1];
+    if (cb < 0 || ce < cb || static_cast<uint32_t>(ce) > a.node_cap - a.n) {
+      if (gid == 0) atomicOr(&a.ctl->error, kErrBadSplit);
+      cb = ce = 0;
+    }
     if (gid == 0) {
       uint32_t i = 0, p = 0;
       if (d0 > 0) {
@@ -237,7 +262,10 @@ __global__ __launch_bounds__(kBlock) void k_init(KArgs a, int32_t src) {
       }
       for (int32_t c = cb; c < ce && i < a.node_cap; ++c) {
         const int32_t cs = a.offsets[a.n + c], cl = a.offsets[a.n + c + 1] - cs;
-        if (cl <= 0) continue;
+        if (cl <= 0) {  // not a table lbg_split_graph wrote
+          atomicOr(&a.ctl->error, kErrBadSplit);
+          continue;
+        }
         a.fr[0].node[i] = src;
         a.fr[0].eprefix[i] = p;
         a.fr[0].estart[i] = cs;
@@ -399,7 +427,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   // A frontier node's own distance comes from the packed state
   // (authoritative); the per-arc filter reads the output array.
   const uint32_t state_len = kMulti ? a.rows : a.n;
-  uint32_t upd = 0, atom = 0, qcount = 0;
+  uint32_t upd = 0, atom = 0, qcount = 0, skip = 0;
   if (!kSssp) refresh_seen(a, L);
 
   const uint32_t ntiles = (Ef + T - 1) / T;
@@ -506,7 +534,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
         const int slot = static_cast<int>(w.wpre[k] + __popc(w.flag[k] & msk)) - 1;
         const uint32_t e = slot >= 0 ? w.base[slot] + s : a.m;
         if (kSssp && slot >= 0 && w.du[slot] == kSsspInf) {
-          // skipped entry (see staging)
+          ++skip;  // skipped entry (see staging)
         } else if (e < a.m) {
           if (kPacked) {
             load_arc<true, kNarrow>(a, e, &vv[r], &ww[r]);
@@ -682,7 +710,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
     merge_base = tn ? atomicAdd(&a.ctl->ctr[nctr], (static_cast<unsigned long long>(tn) << 32) | te) : 0ull;
   __syncthreads();
   f.write(a, nxt, static_cast<uint32_t>(merge_base >> 32) + pn, static_cast<uint32_t>(merge_base) + pe);
-  add_stats(a, upd, atom);
+  add_stats(a, upd, atom, skip);
 }
 
 template <bool kSssp, bool kNarrow, bool kMulti, bool kPacked = false, bool kSplit = false>
@@ -1264,7 +1292,11 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
   const uint32_t cnt = sub == 0 ? nf
                                 : __hip_atomic_load(&a.ctl->sub_cnt[sub % 3], __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->sub_cnt[(sub + 2) % 3] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->sub_cnt[(sub + 2) % 3] = 0u;
+    if (a.hier_trace && cnt && L < kHierTraceLevels && sub < kHierTraceSubs)
+      a.hier_trace[L * kHierTraceSubs + sub] = cnt;
+  }
   if (cnt == 0) return;
   if (!kSssp && sub == 0) refresh_seen(a, L);
   const Frontier cur = a.fr[L & 1];
@@ -1275,11 +1307,12 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
   const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   WaveQueue<kSssp> q{qS[wid], qD[wid], qV[kSssp ? wid : 0], 0u};
   auto flush = [&]() { q.template flush_nodes<false>(a, nxt, nctr); };
-  uint32_t upd = 0, atom = 0;
+  uint32_t upd = 0, atom = 0, skip = 0;
   const unsigned long long w0 = static_cast<unsigned long long>(sub) * mdt;
 
   // entry e of the level: first arc, degree and (SSSP) current distance;
-  // deg = 0 when it was improved again this iteration (relaxed next time)
+  // deg = 0 when it was improved again this iteration (relaxed next time:
+  // its arcs from this sub-iteration's window on count as skipped)
   auto entry = [&](uint32_t e, uint32_t* st, uint32_t* deg, uint32_t* du) {
     const uint32_t p = cur.eprefix[e];
     const uint32_t pn = (e + 1 < nf) ? cur.eprefix[e + 1] : Ef;
@@ -1292,7 +1325,10 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
     *du = 0;
     if (kSssp) {
       const unsigned long long sv = a.dstate[cur.node[e]];
-      if (static_cast<uint32_t>(sv) == L + 1) *deg = 0;
+      if (static_cast<uint32_t>(sv) == L + 1) {
+        skip += *deg > w0 ? static_cast<uint32_t>(*deg - w0) : 0u;
+        *deg = 0;
+      }
       *du = static_cast<uint32_t>(sv >> 32);
     }
   };
@@ -1389,7 +1425,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
     }
   }
   flush();
-  add_stats(a, upd, atom);
+  add_stats(a, upd, atom, skip);
 }
 
 // ---------------------------------------------------------- edge (EP) ----
@@ -1647,6 +1683,22 @@ __global__ __launch_bounds__(kBlock) void k_weight_max(const uint32_t* weights, 
   for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < m; e += gridDim.x * kBlock) mx = max(mx, weights[e]);
   mx = static_cast<uint32_t>(wave_max(static_cast<int32_t>(mx ^ 0x80000000u))) ^ 0x80000000u;  // unsigned max
   if (lane_id() == 0 && mx) atomicMax(&ctl->deg_max, mx);
+}
+
+// Source node of every arc (the COO array the edge-based strategy reads,
+// Section II-B): wavefront w of the grid writes the arcs of nodes w, w + W,
+// ..., 64 consecutive positions per store, so hubs cost many stores of one
+// wavefront but every store is coalesced.  Offsets outside [0, m] are
+// clamped (lbg_validate_csr first on untrusted input).
+__global__ __launch_bounds__(kBlock) void k_coo_sources(const int32_t* offsets, uint32_t n, uint32_t m,
+                                                        int32_t* coo) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t W = gridDim.x * kWaves;
+  for (uint32_t u = blockIdx.x * kWaves + (threadIdx.x >> 6); u < n; u += W) {
+    const int32_t s0 = offsets[u], s1 = offsets[u + 1];
+    const uint32_t b = static_cast<uint32_t>(s0 < 0 ? 0 : s0), e = min(static_cast<uint32_t>(s1 < 0 ? 0 : s1), m);
+    for (uint32_t k = b + lane; k < e; k += 64) coo[k] = static_cast<int32_t>(u);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_arcs(const int32_t* cols, const uint32_t* weights, uint32_t m,

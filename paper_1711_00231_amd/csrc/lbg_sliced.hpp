@@ -305,7 +305,8 @@ template <bool kSssp, bool kNarrow>
 __device__ __forceinline__ void sliced_tiles(const KArgs& a, uint32_t L, const Frontier& cur, uint32_t nf,
                                              uint32_t Ef, uint32_t first, uint32_t W,
                                              WaveLds<kSssp, false>& w, const Frontier& nxt,
-                                             uint32_t& upd, uint32_t& atom, uint32_t& qcount) {
+                                             uint32_t& upd, uint32_t& atom, uint32_t& skip,
+                                             uint32_t& qcount) {
   constexpr int kItems = TileCfg<kSssp>::kItems;
   constexpr uint32_t T = TileCfg<kSssp>::kEdges;
   constexpr int kPay = kSssp ? 1 : 0;
@@ -377,7 +378,7 @@ __device__ __forceinline__ void sliced_tiles(const KArgs& a, uint32_t L, const F
         const int slot = static_cast<int>(w.wpre[k] + __popc(w.flag[k] & msk)) - 1;
         const uint32_t e = slot >= 0 ? w.base[slot] + s : a.m;
         if (kSssp && slot >= 0 && w.du[slot] == kSsspInf) {
-          // skipped entry
+          ++skip;  // skipped entry
         } else if (e < a.m) {
           vv[r] = *at<kNarrow>(a.cols, e);
           if (kSssp) {
@@ -506,15 +507,15 @@ __global__ __launch_bounds__(kBlock) void k_expand_sliced(KArgs a, uint32_t L) {
   WaveLds<kSssp, false>& w = lds[wid];
   Frontier nxt = a.fr[(L + 1) & 1];
   nxt.level = L + 1;
-  uint32_t upd = 0, atom = 0, qcount = 0;
+  uint32_t upd = 0, atom = 0, skip = 0, qcount = 0;
   if (static_cast<uint32_t>(cx) != 0u)
     sliced_tiles<kSssp, kNarrow>(a, L, slice_of(a.fr[L & 1], a, x), static_cast<uint32_t>(cx >> 32),
                                  static_cast<uint32_t>(cx), (blockIdx.x / kXcds) * kWaves + wid,
-                                 ((gridDim.x - x + kXcds - 1) / kXcds) * kWaves, w, nxt, upd, atom, qcount);
+                                 ((gridDim.x - x + kXcds - 1) / kXcds) * kWaves, w, nxt, upd, atom, skip, qcount);
   if (static_cast<uint32_t>(cm) != 0u)
     sliced_tiles<kSssp, kNarrow>(a, L, slice_of(a.fr[L & 1], a, kXcds), static_cast<uint32_t>(cm >> 32),
                                  static_cast<uint32_t>(cm), blockIdx.x * kWaves + wid, gridDim.x * kWaves, w,
-                                 nxt, upd, atom, qcount);
+                                 nxt, upd, atom, skip, qcount);
 
   // Final flush: per list, one reservation for the whole workgroup.
   Flush f;
@@ -558,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_sliced(KArgs a, uint32_t L) {
     if (yn) f.write(a, nxt, y, static_cast<uint32_t>(merge_base[y] >> 32) + bn, static_cast<uint32_t>(merge_base[y]) + be,
                     ss, ds, pn, pe);
   }
-  add_stats(a, upd, atom);
+  add_stats(a, upd, atom, skip);
 }
 
 }  // namespace lbg

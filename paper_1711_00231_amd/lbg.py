@@ -33,7 +33,8 @@ class LbgError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("frontier_entries", ctypes.c_int64), ("edges_scanned", ctypes.c_int64),
-                ("updates", ctypes.c_int64), ("atomics", ctypes.c_int64)]
+                ("updates", ctypes.c_int64), ("atomics", ctypes.c_int64),
+                ("edges_skipped", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -59,7 +60,7 @@ class Profile(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("empty_ms", ctypes.c_double),
                 ("frontier_entries", ctypes.c_int64),
                 ("edges_scanned", ctypes.c_int64), ("updates", ctypes.c_int64),
-                ("atomics", ctypes.c_int64)]
+                ("atomics", ctypes.c_int64), ("edges_skipped", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -78,6 +79,14 @@ def _load():
     lib.lbg_sssp.restype = ctypes.c_int
     lib.lbg_sssp.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, sz, i32, vp,
                              ctypes.POINTER(Stats), vp]
+    lib.lbg_coo_sources.restype = ctypes.c_int
+    lib.lbg_coo_sources.argtypes = [vp, i32, i64, vp, vp]
+    lib.lbg_set_hier_mdt.restype = ctypes.c_int
+    lib.lbg_set_hier_mdt.argtypes = [i32]
+    lib.lbg_get_hier_mdt.restype = i32
+    lib.lbg_get_hier_mdt.argtypes = []
+    lib.lbg_hier_last_schedule.restype = i32
+    lib.lbg_hier_last_schedule.argtypes = [ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32)]
     lib.lbg_pack_arcs.restype = ctypes.c_int
     lib.lbg_pack_arcs.argtypes = [vp, vp, i32, i64, vp, ctypes.POINTER(i32), vp, sz, vp]
     lib.lbg_sssp_packed.restype = ctypes.c_int
@@ -273,13 +282,13 @@ class DeviceGraph:
             self.ordered = order_graph(self, stream=stream)
         return self.ordered
 
-    def ensure_coo(self) -> torch.Tensor:
+    def ensure_coo(self, stream=None) -> torch.Tensor:
+        """The COO source array of the edge-based strategy, built by the
+        library (lbg_coo_sources) once per graph."""
         if self.coo_src is None:
-            deg = (self.offsets[1:] - self.offsets[:-1]).to(torch.int64)
-            self.coo_src = torch.repeat_interleave(
-                torch.arange(self.n, dtype=torch.int32, device=self.offsets.device), deg)
-            if self.coo_src.numel() == 0:
-                self.coo_src = torch.zeros(1, dtype=torch.int32, device=self.offsets.device)
+            coo = torch.empty(max(self.m, 1), dtype=torch.int32, device=self.offsets.device)
+            _check(lib.lbg_coo_sources(_ptr(self.offsets), self.n, self.m, _ptr(coo), _stream(stream)))
+            self.coo_src = coo
         return self.coo_src
 
 
@@ -633,6 +642,28 @@ def profile_read(which) -> dict:
     p = Profile()
     lib.lbg_profile_read(idx, ctypes.byref(p))
     return p.as_dict()
+
+
+def set_hier_mdt(mdt: int) -> None:
+    """Fixed MDT of later LBG_HIER solves (0 = the histogram rule)."""
+    _check(lib.lbg_set_hier_mdt(int(mdt)))
+
+
+def get_hier_mdt() -> int:
+    return int(lib.lbg_get_hier_mdt())
+
+
+def hier_last_schedule(max_levels: int = 64, max_subs: int = 256):
+    """(sizes, mdt) of this thread's last LBG_HIER solve: sizes[l][s] = the
+    sublist size of sub-iteration s of level l (0 past the last), as a numpy
+    int32 array of shape (levels, max_subs)."""
+    import numpy as np
+
+    buf = (ctypes.c_int32 * (max_levels * max_subs))()
+    mdt = ctypes.c_int32(0)
+    nl = int(lib.lbg_hier_last_schedule(buf, max_levels, max_subs, ctypes.byref(mdt)))
+    arr = np.frombuffer(buf, dtype=np.int32).reshape(max_levels, max_subs)[:nl].copy()
+    return arr, int(mdt.value)
 
 
 def set_bins(mdt: int, t_wave: int, t_block: int) -> None:

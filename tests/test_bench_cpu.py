@@ -28,6 +28,10 @@ def test_algorithmic_bytes():
     p = {"edges_scanned": 1000, "updates": 10, "frontier_entries": 7}
     assert bench.algorithmic_bytes("bfs", p) == 8 * 1000 + 20 * 10
     assert bench.algorithmic_bytes("sssp", p) == 12 * 1000 + 4 * 10 + 20 * 7
+    # arcs of entries skipped at staging are never loaded: not charged
+    p["edges_skipped"] = 300
+    assert bench.algorithmic_bytes("sssp", p) == 12 * 700 + 4 * 10 + 20 * 7
+    assert bench.algorithmic_bytes("bfs", p) == 8 * 1000 + 20 * 10
 
 
 def _fake_root(tmp_path, digest_of=None):

@@ -615,16 +615,57 @@ def test_rmat22_full(rmat22, strat):
         assert O.certificate(g.offsets, g.cols, None, s, lv)[0] == 0
 
 
-def test_grid2048_full():
-    """2048x2048 road-like grid (and its no-shortcut companion with ~4000
-    levels): full vectors against the oracle."""
+@pytest.fixture(scope="module")
+def grid2048():
     g = graphgen.grid(2048)
-    srcs = graphgen.sources(g, 2, graphgen.FAMILY_GRID)
-    _check(g, _dev(g), srcs[:1], "balanced")
+    return g, _dev(g), graphgen.sources(g, 16, graphgen.FAMILY_GRID)
+
+
+@pytest.mark.parametrize("strat", FULL_STRATS)
+def test_grid2048_full(grid2048, strat):
+    """2048x2048 road-like grid (10% of edges dropped, 1% shortcuts, the
+    high-diameter configuration): full BFS and SSSP vectors against the
+    oracle for every strategy, each from its own one of the 16 sources."""
+    g, dg, srcs = grid2048
+    _check(g, dg, [int(srcs[FULL_STRATS.index(strat)])], strat)
+
+
+@pytest.mark.parametrize("strat", ["balanced", "binned"])
+def test_grid2048_noshortcut_full(grid2048, strat):
+    """The no-shortcut companion (about 4000 levels of small frontiers): BFS
+    and SSSP against the oracle with the balanced strategy (which runs most
+    levels in the small-frontier kernel) and the degree-binned one (one
+    launch per level throughout)."""
     h = graphgen.grid(2048, shortcut_frac=0)
-    dh = _dev(h)
-    s = int(srcs[1])
-    assert np.array_equal(_gpu_bfs(dh, s, "balanced"), O.bfs(h.offsets, h.cols, s))
+    s = int(grid2048[2][15 - ["balanced", "binned"].index(strat)])
+    _check(h, _dev(h), [s], strat)
+
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_rmat22_all_sources_certified(rmat22, chunk):
+    """Every one of the 64 benchmark sources (16 per chunk): balanced BFS on
+    the input CSR and balanced SSSP on the degree-class ordered copy (the two
+    solves the benchmark times) and on the input CSR, each certified exact by
+    the oracle's O(m) certificate (source at 0, no arc relaxable, tight arcs
+    reach exactly the finite nodes)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    g, dg, srcs = rmat22
+    dg.ensure_ordered()
+    jobs = []
+    for s in srcs[16 * chunk: 16 * (chunk + 1)]:
+        s = int(s)
+        jobs.append((s, None, _gpu_bfs(dg, s, "balanced")))
+        jobs.append((s, g.weights, lbg.sssp(dg, s, ordered=True).cpu().numpy().view(np.uint32)))
+        jobs.append((s, g.weights, _gpu_sssp(dg, s, "balanced")))
+
+    def cert(job):
+        s, w, d = job
+        return s, w is None, O.certificate(g.offsets, g.cols, w, s, d)[0]
+
+    with ThreadPoolExecutor(8) as ex:  # the oracle's C calls release the interpreter lock
+        bad = [(s, bfs) for s, bfs, code in ex.map(cert, jobs) if code != 0]
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("strat", STRATS)
