@@ -1312,8 +1312,9 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
 
   // entry e of the level: first arc, degree and (SSSP) current distance;
   // deg = 0 when it was improved again this iteration (relaxed next time:
-  // its arcs from this sub-iteration's window on count as skipped)
-  auto entry = [&](uint32_t e, uint32_t* st, uint32_t* deg, uint32_t* du) {
+  // its arcs from this sub-iteration's window on count as skipped, by the
+  // one thread that stages the entry for the grid: count_skip)
+  auto entry = [&](uint32_t e, uint32_t* st, uint32_t* deg, uint32_t* du, bool count_skip) {
     const uint32_t p = cur.eprefix[e];
     const uint32_t pn = (e + 1 < nf) ? cur.eprefix[e + 1] : Ef;
     *st = static_cast<uint32_t>(cur.estart[e]);
@@ -1326,7 +1327,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
     if (kSssp) {
       const unsigned long long sv = a.dstate[cur.node[e]];
       if (static_cast<uint32_t>(sv) == L + 1) {
-        skip += *deg > w0 ? static_cast<uint32_t>(*deg - w0) : 0u;
+        if (count_skip) skip += *deg > w0 ? static_cast<uint32_t>(*deg - w0) : 0u;
         *deg = 0;
       }
       *du = static_cast<uint32_t>(sv >> 32);
@@ -1347,7 +1348,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
     for (uint32_t base = blockIdx.x * kBlock; base < cnt; base += gridDim.x * kBlock) {
       const uint32_t i = base + tid;
       uint32_t st = 0, deg = 0, du = 0;
-      if (i < cnt) entry(sub == 0 ? i : static_cast<uint32_t>(in[i]), &st, &deg, &du);
+      if (i < cnt) entry(sub == 0 ? i : static_cast<uint32_t>(in[i]), &st, &deg, &du, true);
       const unsigned long long lo = w0 < deg ? w0 : deg;
       const unsigned long long hi = (w0 + mdt) < deg ? (w0 + mdt) : deg;
       const uint32_t len = static_cast<uint32_t>(hi - lo);
@@ -1369,11 +1370,12 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
     }
   } else {
     // hand-over: all remaining arcs of the (< kHierWd) active nodes, balanced
+    // (every workgroup stages every entry; workgroup 0 counts the skips)
     uint32_t st = 0, deg = 0, du = 0;
     for (uint32_t j = tid; j < kHierWd; j += kBlock) {
       uint32_t rem = 0, s0 = 0, d0 = 0;
       if (j < cnt) {
-        entry(sub == 0 ? j : static_cast<uint32_t>(in[j]), &st, &deg, &du);
+        entry(sub == 0 ? j : static_cast<uint32_t>(in[j]), &st, &deg, &du, blockIdx.x == 0);
         rem = deg > w0 ? static_cast<uint32_t>(deg - w0) : 0u;
         s0 = st + static_cast<uint32_t>(deg > w0 ? w0 : deg);
         d0 = du;

@@ -72,8 +72,12 @@ def test_cpu_baseline_record():
 
     g = graphgen.uniform(10)
     rec = bench.cpu_baseline(g, np.array([0, 1, 2], dtype=np.int32), budget_s=0.0)
-    assert rec["kind"] == "oracle" and rec["cores"] == 1 and rec["unit"] == "GTEPS"
-    assert rec["value"] > 0 and "1 source(s)" in rec["sample"]
+    host = bench.host_info()
+    assert rec["kind"] == "oracle" and rec["unit"] == "GTEPS"
+    assert rec["cores"] == host["nproc"] >= 1 and rec["host"] == host
+    assert rec["value"] > 0 and f"{host['nproc']} sources" in rec["sample"]
+    st = rec["single_thread"]
+    assert st["sources"] == 1 and st["bfs_ms_p50"] >= 0 and st["sssp_ms_p50"] >= 0 and st["gteps_hmean"] > 0
 
 
 def test_workload_table():

@@ -102,6 +102,11 @@ def test_skipped_arcs_accounting():
         assert st["edges_scanned"] - st["edges_skipped"] >= reached_arcs
         assert sb["edges_skipped"] == 0 and sb["edges_scanned"] == reached_arcs
         assert np.array_equal(d.cpu().numpy().view(np.uint32), O.dijkstra(g.offsets, g.cols, g.weights, int(s)))
+        # the hierarchical strategy skips within windows: counted once per
+        # entry, however many workgroups stage it at the hand-over
+        dh, sh = lbg.sssp(dg, int(s), strategy="hier", stats=True)
+        assert 0 <= sh["edges_skipped"] <= sh["edges_scanned"]
+        assert np.array_equal(dh.cpu().numpy().view(np.uint32), d.cpu().numpy().view(np.uint32))
 
 
 @pytest.mark.parametrize("name", ["rmat14", "uniform12", "empty-tail"])
