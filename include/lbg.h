@@ -164,6 +164,34 @@ int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weight
              int64_t m, int32_t src, uint32_t* dist_out, void* workspace, size_t workspace_bytes,
              int32_t strategy, const int32_t* coo_src, lbg_stats* stats, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lbg_sssp without a
+ * workspace argument.  The call makes no device or host allocation of any
+ * kind (no hipMalloc, hipFree, hipHostMalloc, event creation or library
+ * allocator); its workspace is a file-scope device array of
+ * LBG_NOALLOC_SCRATCH_BYTES bytes that every GPU the library runs on holds
+ * from the library's first use on it until the process ends.
+ *   - Sizes: lbg_workspace_bytes(n, m, strategy, 1) must not exceed
+ *     LBG_NOALLOC_SCRATCH_BYTES (64 MiB: e.g. R-MAT scale 20, n = 2^20 with
+ *     31 M arcs, fits; scale 22 does not); larger problems return
+ *     LBG_ENOMEM before any launch, with dist_out untouched.
+ *   - strategy: LBG_AUTO, LBG_BALANCED, LBG_NODE, LBG_BINNED or LBG_HIER
+ *     (the ones that need no other input); others return LBG_EINVAL.
+ *   - Results are identical to lbg_sssp's.  The solve is stream-ordered on
+ *     `stream` and returns when dist_out is written, as lbg_sssp does; the
+ *     control block is read back through pageable host memory.  Launch
+ *     timing (lbg_profile_enable) does not apply to these calls, and an
+ *     LBG_HIER call leaves lbg_hier_last_schedule untouched.
+ *   - Every call on one GPU uses that GPU's one array, and each call
+ *     re-initialises everything it reads there: calls that overlap on one
+ *     GPU (other host threads, other streams) race and must be serialised
+ *     by the caller.
+ * Other arguments and errors as for lbg_sssp. */
+#define LBG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lbg_sssp_noalloc(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                     int64_t m, int32_t src, uint32_t* dist_out, int32_t strategy, lbg_stats* stats,
+                     void* stream);
+
 /* COO source array of a CSR graph (what LBG_EDGE and LBG_EDGE_NOCHUNK
  * read beside the CSR; Section II-B): coo_out[e] = the node u with
  * offsets[u] <= e < offsets[u + 1], for every arc e in [0, m).  coo_out is a

@@ -326,6 +326,7 @@ struct Problem {
   const int32_t* child_base = nullptr;  // lbg_bfs_split / lbg_sssp_split: the split graph's
   int64_t children = 0;                 // child table and child count
   const int32_t* node_map = nullptr;    // lbg_sssp_ordered: new id of every original node
+  bool no_alloc = false;                // lbg_sssp_noalloc: no allocating call of any kind
 };
 
 int check_common(const Problem& P) {
@@ -426,11 +427,14 @@ int solve(const Problem& P) {
   bool profiling;
   {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    profiling = g_prof_on;
+    profiling = g_prof_on && !P.no_alloc;  // launch timing creates events
   }
   a.count_stats = (P.stats || profiling) ? 1u : 0u;
 
-  Ctl* host = pinned_ctl();
+  // the control block is read back into pinned memory allocated on first
+  // use, or, for callers that cannot allocate, into this thread's pageable copy
+  thread_local Ctl pageable_ctl;
+  Ctl* host = P.no_alloc ? &pageable_ctl : pinned_ctl();
   if (!host) return fail(LBG_EHIP, "hipHostMalloc of the readback word failed");
 
   const hipStream_t st = P.stream;
@@ -614,7 +618,7 @@ int solve(const Problem& P) {
   }
 
   g_level_hint[P.is_sssp ? 1 : 0] = used_small ? 0u : host->levels;
-  if (strat == LBG_HIER) {
+  if (strat == LBG_HIER && !P.no_alloc) {
     g_hier_sched.assign(static_cast<size_t>(lbg::kHierTraceLevels) * lbg::kHierTraceSubs, 0u);
     HIP_TRY(hipMemcpyAsync(g_hier_sched.data(), a.hier_trace, sizeof(uint32_t) * g_hier_sched.size(),
                            hipMemcpyDeviceToHost, st));
@@ -1234,6 +1238,37 @@ void lbg_engine_destroy(lbg_engine* e) {
 namespace {
 }  // namespace
 
+// Scratch of lbg_sssp_noalloc: the workspace of one solve, in a file-scope
+// device array that every GPU the library runs on holds until the process
+// ends.  Host code never passes the array's name to a kernel or a copy (on
+// the host it only stands in for the symbol); it uses the device address
+// hipGetSymbolAddress gives, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[LBG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of this device's copy of `scratch` (the current device's).
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(LBG_EINVAL, "device %d outside the 64 the library tracks", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LBG_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t lbg_workspace_bytes(int32_t n, int64_t m, int32_t strategy, int32_t is_sssp) {
@@ -1254,6 +1289,29 @@ int lbg_sssp(const int32_t* offsets, const int32_t* cols, const uint32_t* weight
              int32_t strategy, const int32_t* coo_src, lbg_stats* stats, void* stream) {
   Problem P{offsets, cols, weights, coo_src, n, m, src, dist_out, workspace, workspace_bytes,
             strategy, 1, stats, static_cast<hipStream_t>(stream)};
+  return solve(P);
+}
+
+int lbg_sssp_noalloc(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, int32_t n,
+                     int64_t m, int32_t src, uint32_t* dist_out, int32_t strategy, lbg_stats* stats,
+                     void* stream) {
+  const int32_t s = strategy_ok(strategy) ? resolve(strategy) : strategy;
+  if (s != LBG_BALANCED && s != LBG_NODE && s != LBG_BINNED && s != LBG_HIER)
+    return fail(LBG_EINVAL, "lbg_sssp_noalloc runs LBG_AUTO, LBG_BALANCED, LBG_NODE, LBG_BINNED or LBG_HIER "
+                            "(got %d)", strategy);
+  if (n > 0 && m >= 0 && m <= INT32_MAX) {
+    const size_t need = layout(n, m, strategy, 1).total;
+    if (need > LBG_NOALLOC_SCRATCH_BYTES)
+      return fail(LBG_ENOMEM, "lbg_sssp_noalloc: n = %d, m = %lld need %zu bytes of scratch, above its "
+                  "maximum of %zu", n, static_cast<long long>(m), need,
+                  static_cast<size_t>(LBG_NOALLOC_SCRATCH_BYTES));
+  }
+  void* ws = nullptr;
+  const int rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  Problem P{offsets, cols, weights, nullptr, n, m, src, dist_out, ws, LBG_NOALLOC_SCRATCH_BYTES,
+            strategy, 1, stats, static_cast<hipStream_t>(stream)};
+  P.no_alloc = true;
   return solve(P);
 }
 

@@ -22,6 +22,7 @@ STRATEGIES = {"auto": AUTO, "node": NODE, "edge": EDGE, "balanced": BALANCED, "b
               "split": SPLIT}
 BFS_INF = 2**31 - 1
 SSSP_INF = 2**32 - 1
+NOALLOC_SCRATCH_BYTES = 64 << 20  # LBG_NOALLOC_SCRATCH_BYTES
 
 
 class LbgError(RuntimeError):
@@ -79,6 +80,8 @@ def _load():
     lib.lbg_sssp.restype = ctypes.c_int
     lib.lbg_sssp.argtypes = [vp, vp, vp, i32, i64, i32, vp, vp, sz, i32, vp,
                              ctypes.POINTER(Stats), vp]
+    lib.lbg_sssp_noalloc.restype = ctypes.c_int
+    lib.lbg_sssp_noalloc.argtypes = [vp, vp, vp, i32, i64, i32, vp, i32, ctypes.POINTER(Stats), vp]
     lib.lbg_coo_sources.restype = ctypes.c_int
     lib.lbg_coo_sources.argtypes = [vp, i32, i64, vp, vp]
     lib.lbg_set_hier_mdt.restype = ctypes.c_int
@@ -501,6 +504,23 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
         rc = lib.lbg_sssp(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(src),
                           _ptr(out), _ptr(ws), ws.numel(), s, _ptr(coo),
                           ctypes.byref(st) if stats else None, _stream(stream))
+    _check(rc)
+    return (out, st.as_dict()) if stats else out
+
+
+def sssp_noalloc(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None = None,
+                 stats: bool = False, stream=None):
+    """lbg_sssp_noalloc: SSSP whose workspace is the library's own static
+    device array (no allocation in the call; sizes up to
+    NOALLOC_SCRATCH_BYTES of workspace).  ``out`` must be given by callers
+    that cannot allocate; calls that overlap on one GPU race."""
+    if g.weights is None:
+        raise ValueError("sssp needs weights")
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    st = Stats()
+    rc = lib.lbg_sssp_noalloc(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(src), _ptr(out),
+                              _strategy(strategy), ctypes.byref(st) if stats else None, _stream(stream))
     _check(rc)
     return (out, st.as_dict()) if stats else out
 

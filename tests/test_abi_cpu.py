@@ -129,6 +129,23 @@ def test_sssp_argument_errors():
     assert "src" in lib.lbg_last_error().decode()
 
 
+def test_sssp_noalloc_limits_on_the_host():
+    """The no-allocation SSSP refuses, before touching a device, what its
+    static scratch cannot hold and the strategies that need other inputs."""
+    cap = lbgmod.NOALLOC_SCRATCH_BYTES
+
+    def call(n, m, strategy=lbgmod.BALANCED):
+        return lib.lbg_sssp_noalloc(FAKE, FAKE, FAKE, n, m, 0, FAKE, strategy, None, None)
+
+    # R-MAT scale 20 fits, scale 22 does not
+    assert lbgmod.workspace_bytes(1 << 20, 31_400_000, "balanced", True) <= cap
+    assert lbgmod.workspace_bytes(1 << 22, 128_307_136, "balanced", True) > cap
+    assert call(1 << 22, 128_307_136) == lbgmod.ENOMEM
+    assert "maximum" in lib.lbg_last_error().decode()
+    for s in (lbgmod.EDGE, lbgmod.EDGE_NOCHUNK, lbgmod.SLICED, lbgmod.SPLIT, 9, -1):
+        assert call(100, 200, s) == lbgmod.EINVAL
+
+
 def test_validate_csr_argument_errors():
     assert lib.lbg_validate_csr(FAKE, FAKE, 0, 5, WS, 1 << 20, None) == lbgmod.EINVAL
     assert lib.lbg_validate_csr(FAKE, FAKE, 5, -2, WS, 1 << 20, None) == lbgmod.ERANGE
