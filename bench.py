@@ -27,14 +27,21 @@ sample of the same sources: all host cores at once (value, cores = threads
 used) and a single-thread leg (per-source medians), with the host's core
 count and CPU model.
 
-batched / serving (extra objects on the same line; full sizes with
---mode batch / --mode serve):
-  batched: the same queries as one lbg_batch_solve call vs one plain call
-  per query, over packed instances of uneven size.
-  serving: a Poisson stream of BFS/SSSP requests (70/30) over resident
-  graphs plus per-request uploaded graphs, served with continuous batching;
-  p50/p99 latency at fractions of the saturation rate of plain per-query
-  launches.
+extra objects on the same line (--no-extras skips them; --mode batch /
+--mode serve run the full batched and serving sweeps alone):
+  strategies: node- vs edge-based vs hierarchical vs balanced vs degree-
+  binned vs destination-sliced vs split-graph solves on the same graph.
+  grid: the 2048x2048 high-diameter grid (1 % shortcuts) and its
+  no-shortcut companion, BFS and SSSP from 4 of the 16 seeded sources.
+  batched: 256 instances of uneven size (n up to 2^18), 4 sources each,
+  BFS + SSSP: the 2,048 solves as one lbg_batch_solve call vs one plain call
+  per query.
+  serving: resident R-MAT 20/22/24 plus per-request uploaded uniform graphs;
+  a Poisson stream of BFS/SSSP requests (70/30) served with continuous
+  batching (overlapping plain solves for the large instances, the engine
+  for the rest) and, at 0.5x, with every resident instance in the engine;
+  p50/p99 latency beside the same arrivals served FCFS by plain per-query
+  launches, at fractions of the plain saturation rate.
 """
 from __future__ import annotations
 
@@ -427,7 +434,7 @@ def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
                 queries.append((int(nb[i] + s), int(nb[i]), int(nb[i + 1]), kind))
     ws = lbg.Workspace(dev)
     ws1 = lbg.Workspace(dev)
-    out = lbg.batch_solve(dg, queries, workspace=ws)  # warm-up + reached-arc count
+    out, bst = lbg.batch_solve(dg, queries, workspace=ws, stats=True)  # warm-up + reached-arc count
     deg = torch.from_numpy(np.diff(u.offsets.astype(np.int64))).to(dev)
     reached = 0
     off = 0
@@ -474,6 +481,7 @@ def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
             "graph_batched_gteps": round(reached / gt / 1e9, 4),
             "plain_gteps": round(reached / tp / 1e9, 4),
             "speedup": round(tp / bt, 3), "graph_speedup": round(tp / gt, 3),
+            "levels": bst["levels"], "graph_launches_per_batch": -(-bst["levels"] // 64),
             "plain_query_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
             "plain_query_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 4),
             "workload": f"{count} instances (half R-MAT scale U[10,{hi_exp}] ef 16 symmetrised, "
@@ -483,7 +491,13 @@ def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
 
 # -------------------------------------------------------------- serving --
 def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_count=8,
-              big_arcs=1 << 23):
+              big_arcs=1 << 23, workers=3, engine_only_fraction=None):
+    """Serving over resident R-MAT instances plus per-request uploads.
+    Instances of at least big_arcs arcs are served by a plain lane of
+    `workers` solves that run at once (queries overlap on the device), the
+    rest, and every upload, are batched by the engine.  engine_only_fraction:
+    also serve that load with every resident instance batched in the engine
+    and no plain lane, for comparison."""
     import graphgen
     from paper_1711_00231_amd import serve
 
@@ -496,19 +510,29 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
     # the small ones are also packed, with the upload regions, for the engine
     singles = {nm: lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
                for nm, g in zip(names, resident)}
-    small = [(nm, g) for nm, g in zip(names, resident) if g.m < big_arcs]
-    u, nb, eb = graphgen.pack([g for _, g in small])
     NC, MC, R = (1 << 16) + 1, (1 << 16) * 8, 8
-    off_e, cols_e, w_e = serve.UploadArena.empty_arrays(R, NC, MC, u.n, u.m)
-    off = np.concatenate([u.offsets[:-1].astype(np.int64), off_e, [u.m + R * MC]])
-    dg = lbg.DeviceGraph.from_numpy(off, np.concatenate([u.cols, cols_e]),
-                                    np.concatenate([u.weights, w_e]), device=dev)
-    del off, off_e, cols_e, w_e
+
+    def engine_for(packed):
+        """Engine over the packed instances (name, graph) plus the upload
+        regions; returns (engine, packed device graph, pack, instance map)."""
+        u, nb, eb = graphgen.pack([g for _, g in packed])
+        off_e, cols_e, w_e = serve.UploadArena.empty_arrays(R, NC, MC, u.n, u.m)
+        off = np.concatenate([u.offsets[:-1].astype(np.int64), off_e, [u.m + R * MC]])
+        dg = lbg.DeviceGraph.from_numpy(off, np.concatenate([u.cols, cols_e]),
+                                        np.concatenate([u.weights, w_e]), device=dev)
+        del off, off_e, cols_e, w_e
+        inst = {nm: serve.Instance(0, g.n, g.m) for nm, g in zip(names, resident)}
+        for i, (nm, g) in enumerate(packed):
+            inst[nm] = serve.Instance(int(nb[i]), int(nb[i + 1]), int(eb[i + 1] - eb[i]))
+        max_rows = 6 * max([g.n for _, g in packed] + [1]) + 16 * NC
+        eng = lbg.Engine(dg, max_queries=64, max_rows=max_rows,
+                         max_level_arcs=min(2**32 - 1, 8 * (u.m + R * MC)))
+        return eng, dg, u, inst
+
+    small = [(nm, g) for nm, g in zip(names, resident) if g.m < big_arcs]
+    eng, dg, u, inst = engine_for(small)
     log(f"serve: resident scales {scales} ({len(small)} batched), packed n={u.n} m={u.m} "
         f"built in {time.perf_counter() - t0:.1f}s")
-    inst = {nm: serve.Instance(0, g.n, g.m) for nm, g in zip(names, resident)}
-    for i, (nm, g) in enumerate(small):
-        inst[nm] = serve.Instance(int(nb[i]), int(nb[i + 1]), int(eb[i + 1] - eb[i]))
     srcs = {nm: graphgen.sources(g, 64, graphgen.FAMILY_SERVE, salt=s)
             for nm, s, g in zip(names, scales, resident)}
     # saturation of plain per-query launches: mean service time of the mix
@@ -538,12 +562,9 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - t)
     sat = 1.0 / float(np.mean(svc))
-    max_rows = 6 * max([g.n for _, g in small] + [1]) + 16 * NC
-    eng = lbg.Engine(dg, max_queries=64, max_rows=max_rows,
-                     max_level_arcs=min(2**32 - 1, 8 * (u.m + R * MC)))
     # the plain lane holds every resident instance: large ones always go
     # there, small ones only when the engine and the lane are both idle
-    lane = serve.gpu_plain_lane(singles, big_arcs, ordered_sssp=True)
+    lane = serve.gpu_plain_lane(singles, big_arcs, ordered_sssp=True, workers=workers)
 
     def plain_serve(reqs):
         """The same arrivals served FCFS by one plain call per request (upload
@@ -562,35 +583,152 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
                 "plain_p99_ms": round(float(np.percentile(lat, 99)), 4),
                 "plain_qps": round(len(reqs) / wall, 2)}
 
+    def requests_at(frac):
+        return serve.poisson_requests(sat * frac, requests_per_point, inst, upload_graphs=uploads,
+                                      upload_share=0.25, seed=int(frac * 1000), sources=srcs)
+
     points = []
     for frac in fractions:
-        qps = sat * frac
-        reqs = serve.poisson_requests(qps, requests_per_point, inst, upload_graphs=uploads,
-                                      upload_share=0.25, seed=int(frac * 1000), sources=srcs)
+        reqs = requests_at(frac)
         arena = serve.UploadArena(dg, u.n, u.m, R, NC, MC)
         rep = serve.Server(eng, inst, upload=arena, plain=lane, idle_bypass=True,
                            levels_per_step=2).run(reqs)
         s = rep.summary()
-        s["offered_qps"] = round(qps, 2)
+        s["offered_qps"] = round(sat * frac, 2)
         s["fraction_of_plain_saturation"] = frac
         s.update(plain_serve(reqs))
         points.append(s)
         log(f"serve {frac:.2f} x saturation: {s}")
     eng.close()
-    return {"plain_saturation_qps": round(sat, 2),
-            "plain_service_ms_p50": round(float(np.percentile(svc, 50)) * 1e3, 4),
-            "plain_service_ms_p99": round(float(np.percentile(svc, 99)) * 1e3, 4),
-            "points": points,
-            "workload": f"resident R-MAT scales {list(scales)} (ef 16, symmetrised, weights "
-                        f"U[1,255]) + per-request uploaded uniform graphs n in [2^12, 2^16]; "
-                        f"Poisson arrivals, 70% BFS / 30% SSSP, 25% uploads; "
-                        f"{requests_per_point} requests per point; gteps counts instance arcs; "
-                        f"instances of >= {big_arcs} arcs are served by plain solves on a second "
-                        f"stream, the rest are batched unless the engine and that stream are both "
-                        f"idle (then a resident query runs plain: 'bypassed'); plain solves of "
-                        f"resident instances run SSSP on their degree-class ordered copy; the engine advances "
-                        f"2 levels per step; plain_* = the same "
-                        f"arrivals served FCFS by one plain call each"}
+    out = {"plain_saturation_qps": round(sat, 2),
+           "plain_service_ms_p50": round(float(np.percentile(svc, 50)) * 1e3, 4),
+           "plain_service_ms_p99": round(float(np.percentile(svc, 99)) * 1e3, 4),
+           "lane_workers": workers,
+           "points": points,
+           "workload": f"resident R-MAT scales {list(scales)} (ef 16, symmetrised, weights "
+                       f"U[1,255]) + per-request uploaded uniform graphs n in [2^12, 2^16]; "
+                       f"Poisson arrivals, 70% BFS / 30% SSSP, 25% uploads; "
+                       f"{requests_per_point} requests per point; gteps counts instance arcs; "
+                       f"instances of >= {big_arcs} arcs are served by a plain lane of {workers} "
+                       f"solves that run at once (each on its own stream and workspace: queries "
+                       f"overlap on the device), the rest are batched by the engine unless the "
+                       f"engine and the lane are both idle (then a resident query runs plain: "
+                       f"'bypassed'); plain solves of resident instances run SSSP on their "
+                       f"degree-class ordered copy; the engine advances 2 levels per step; "
+                       f"plain_* = the same arrivals served FCFS by one plain call each"}
+    if engine_only_fraction is not None:
+        # every resident instance batched by the engine, no plain lane
+        del eng, dg
+        torch.cuda.empty_cache()
+        eng2, dg2, u2, inst2 = engine_for(list(zip(names, resident)))
+        reqs = serve.poisson_requests(sat * engine_only_fraction, requests_per_point, inst2,
+                                      upload_graphs=uploads, upload_share=0.25,
+                                      seed=int(engine_only_fraction * 1000), sources=srcs)
+        arena = serve.UploadArena(dg2, u2.n, u2.m, R, NC, MC)
+        rep = serve.Server(eng2, inst2, upload=arena, levels_per_step=2).run(reqs)
+        s = rep.summary()
+        s["offered_qps"] = round(sat * engine_only_fraction, 2)
+        s["fraction_of_plain_saturation"] = engine_only_fraction
+        s.update(plain_serve(reqs))
+        eng2.close()
+        out["engine_only"] = s
+        log(f"serve, engine only, {engine_only_fraction:.2f} x saturation: {s}")
+    return out
+
+
+# ----------------------------------------------------------------- grid --
+def run_grid(lbg, torch, dev, sources=4):
+    """The high-diameter configuration: 2048x2048 grid with 1 % shortcuts
+    and its no-shortcut companion, balanced BFS and SSSP from the first
+    `sources` of the 16 seeded sources (one warm-up solve each)."""
+    out = {}
+    for name in ("grid2048", "grid2048-noshortcut"):
+        g, srcs, desc, _ = make_workload(name)
+        dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
+        ws = lbg.Workspace(dev)
+        deg = torch.from_numpy(g.degrees).to(dev)
+        res = {"workload": desc, "n": g.n, "m": g.m}
+        for kind, f in (("bfs", lbg.bfs), ("sssp", lbg.sssp)):
+            ts, arcs, levels = [], 0, []
+            for s in srcs[:sources]:
+                s = int(s)
+                lv = lbg.bfs(dg, s, workspace=ws)
+                arcs += int(deg[lv != lbg.BFS_INF].sum().item())
+                f(dg, s, workspace=ws)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, st = f(dg, s, workspace=ws, stats=True)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+                levels.append(st["levels"])
+            res[f"{kind}_ms_p50"] = round(float(np.median(ts)) * 1e3, 3)
+            res[f"{kind}_gteps"] = round(arcs / sum(ts) / 1e9, 4)
+            res[f"{kind}_levels"] = levels
+        out[name] = res
+        log(f"grid {name}: {res}")
+    return out
+
+
+# ------------------------------------------------------------- capacity --
+def run_capacity(lbg, torch, dev, scales=(24, 26), sources=2):
+    """Largest R-MAT instances on one GPU (the space argument of the paper's
+    Table I on 288 GB): per scale, the device bytes of the CSR, of the
+    balanced and the edge-based workspaces (the latter with its COO array)
+    as lbg_workspace_bytes gives them and as allocated, and balanced and
+    edge-based BFS / SSSP from `sources` seeded sources, every result
+    certified exact by the oracle's O(m) certificate.  Scale 26 is the
+    largest whose arc count fits int32 CSR offsets."""
+    import graphgen
+    import oracle
+
+    O = oracle.get()
+    out = []
+    for sc in scales:
+        t0 = time.perf_counter()
+        g = graphgen.rmat(sc)
+        gen_s = time.perf_counter() - t0
+        log(f"capacity: R-MAT scale {sc} n={g.n} m={g.m} generated in {gen_s:.1f}s")
+        srcs = graphgen.sources(g, sources, graphgen.FAMILY_RMAT)
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        dg = lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights, device=dev)
+        graph_bytes = torch.cuda.memory_allocated() - base
+        rec = {"scale": sc, "n": g.n, "m": g.m, "generate_s": round(gen_s, 1), "graph_bytes": graph_bytes,
+               "int32_offsets_headroom": round((2**31 - 1) / g.m, 3)}
+        for strat in ("balanced", "edge"):
+            wb = max(lbg.workspace_bytes(g.n, g.m, strat, False), lbg.workspace_bytes(g.n, g.m, strat, True))
+            ws = lbg.Workspace(dev)
+            before = torch.cuda.memory_allocated()
+            ws.get(wb)
+            if strat == "edge":
+                dg.ensure_coo()
+            rec[f"{strat}_workspace_bytes"] = wb
+            rec[f"{strat}_allocated_bytes"] = torch.cuda.memory_allocated() - before
+            for kind, f, w in (("bfs", lbg.bfs, None), ("sssp", lbg.sssp, g.weights)):
+                ts, ok = [], True
+                for s in srcs:
+                    s = int(s)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    res = f(dg, s, strategy=strat, workspace=ws)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t)
+                    d = res.cpu().numpy()
+                    if kind == "sssp":
+                        d = d.view(np.uint32)
+                    ok = ok and O.certificate(g.offsets, g.cols, w, s, d)[0] == 0
+                rec[f"{strat}_{kind}_ms"] = [round(x * 1e3, 2) for x in ts]
+                rec[f"{strat}_{kind}_certified"] = bool(ok)
+                log(f"capacity scale {sc} {strat} {kind}: {rec[f'{strat}_{kind}_ms']} ms, certified {ok}")
+            del ws
+            torch.cuda.empty_cache()
+        rec["peak_allocated_bytes"] = torch.cuda.max_memory_allocated() - base
+        out.append(rec)
+        log(f"capacity: {rec}")
+        del dg, g
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -598,7 +736,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "capacity"])
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--strategy", default="balanced")
     ap.add_argument("--slice-min", type=int, default=None,
@@ -639,6 +777,15 @@ def main():
                           "dtype": "u32", "data": "synthetic", "vs_baseline": None,
                           "config": {"workload": res["workload"]}, "batched": res}), flush=True)
         return
+    if args.mode == "capacity":
+        res = run_capacity(lbg, torch, dev)
+        print(json.dumps({"metric": "largest R-MAT instance solved and certified", "value": res[-1]["scale"],
+                          "unit": "scale", "n_gpus": 1, "higher_is_better": True, "dtype": "u32",
+                          "data": "synthetic", "vs_baseline": None,
+                          "config": {"workload": "R-MAT scales 24 and 26, ef 16, symmetrised, "
+                                                 "weights U[1,255], 2 sources, balanced and edge-based"},
+                          "capacity": res}), flush=True)
+        return
     if args.mode == "serve":
         res = run_serve(lbg, torch, dev, scales=(20, 22, 24),
                         fractions=(0.25, 0.5, 0.75, 1.0, 1.25), requests_per_point=2000)
@@ -653,11 +800,16 @@ def main():
     if not args.no_extras:
         log("strategy comparison")
         out["strategies"] = run_strategies(lbg, torch, g, srcs, dev)
-        log("compact batched comparison")
-        out["batched"] = run_batch(lbg, torch, dev, count=64, sources_per_instance=4, hi_exp=16)
-        log("compact serving run")
-        out["serving"] = run_serve(lbg, torch, dev, scales=(18, 20), fractions=(0.5, 1.0),
-                                   requests_per_point=300, upload_count=4)
+        log("high-diameter grids")
+        out["grid"] = run_grid(lbg, torch, dev)
+        torch.cuda.empty_cache()
+        log("batched comparison (256 instances, 2,048 solves)")
+        out["batched"] = run_batch(lbg, torch, dev, count=256, sources_per_instance=4, hi_exp=18)
+        torch.cuda.empty_cache()
+        log("serving (resident R-MAT 20/22/24 + uploads)")
+        out["serving"] = run_serve(lbg, torch, dev, scales=(20, 22, 24), fractions=(0.5, 1.0),
+                                   requests_per_point=400, engine_only_fraction=0.5)
+        torch.cuda.empty_cache()
     if args.cpu_budget > 0:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(g, srcs, args.cpu_budget)

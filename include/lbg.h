@@ -502,14 +502,17 @@ int lbg_batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t*
                     lbg_stats* stats, void* stream);
 
 /* lbg_batch_solve with the level loop as a HIP graph: one instantiated graph
- * runs 16 levels (the expansion reads its level from the control block), moves
+ * runs 64 levels (the expansion reads its level from the control block; a
+ * level whose worklist is empty returns at once), moves
  * the level base on, writes the rows out once the worklist is empty and reads
  * the control block back; the host replays it until the batch is done.  The
  * executable graph is cached per host thread and reused while every argument
  * stays the same (same buffers, sizes and queries' workspace layout); a call
  * with other arguments rebuilds it.  Same arguments, results and errors as
  * lbg_batch_solve.  For callers that launch many batches: the host issues one
- * graph launch per 16 levels instead of 16 kernel launches. */
+ * graph launch per 64 levels instead of 64 kernel launches, so a batch of at
+ * most 64 levels (every query's BFS depth and SSSP iteration count) is one
+ * graph launch and one read-back. */
 int lbg_batch_solve_graph(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
                           int32_t n, int64_t m, const lbg_query* queries, int32_t num_queries,
                           uint32_t* out, int64_t total_rows, int64_t total_arcs, void* workspace,

@@ -714,7 +714,7 @@ BatchLayout batch_layout(int32_t num_queries, int64_t rows, int64_t total_arcs) 
 // expansion launches, the level advance, the conditional write-out and the
 // read-back of the control block.  Cached per thread and reused while the
 // launch arguments stay the same (they are copied into the graph).
-constexpr uint32_t kGraphLevels = 16;
+constexpr uint32_t kGraphLevels = 64;
 
 struct GraphCache {
   std::vector<char> key;

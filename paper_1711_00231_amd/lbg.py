@@ -547,7 +547,7 @@ def batch_solve(g: DeviceGraph, queries, out: torch.Tensor | None = None, total_
                 graph: bool = False):
     """Solve many BFS (kind 0) / SSSP (kind 1) queries over a packed graph in
     one level-synchronous batch (see lbg_batch_solve; graph=True replays a
-    cached HIP graph of 16 levels, lbg_batch_solve_graph).  ``queries``: sequence
+    cached HIP graph of 64 levels, lbg_batch_solve_graph).  ``queries``: sequence
     of (src, lo, hi, kind[, out_off]) with global node ids.  Returns the int32
     result tensor (BFS rows: levels; SSSP rows: uint32 bit patterns) or
     (tensor, stats)."""

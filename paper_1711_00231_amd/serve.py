@@ -141,23 +141,27 @@ class ServeReport:
 
 
 class PlainLane:
-    """Queries on large instances, served first-come first-served by one
-    plain solve each from a worker thread.  solve(request, keep) runs the
-    query to completion (the GPU binding releases the interpreter lock
-    meanwhile) and returns its result row when keep is true; `big_arcs` is
-    the size from which an instance goes here.  names: the resident
-    instances solve() can serve (None: all); a server with idle_bypass
-    sends small ones here only while everything is idle."""
+    """Queries on large instances, each served by one plain solve from a
+    worker thread, taken first-come first-served from one queue.
+    solve(request, keep) runs the query to completion (the GPU binding
+    releases the interpreter lock meanwhile) and returns its result row when
+    keep is true.  A sequence of such callables gives one worker thread
+    each (each with its own stream, workspace and output on the GPU): a
+    query that arrives while others run starts as soon as a worker is free,
+    and its work overlaps theirs on the device.  `big_arcs` is the size
+    from which an instance goes here.  names: the resident instances the
+    solvers can serve (None: all); a server with idle_bypass sends small
+    ones here only while everything is idle."""
 
     def __init__(self, solve, big_arcs: int, names=None):
-        self.solve = solve
+        self.solvers = list(solve) if isinstance(solve, (list, tuple)) else [solve]
         self.big_arcs = int(big_arcs)
         self.names = None if names is None else set(names)
         self._q: queue.Queue = queue.Queue()
         self._lock = threading.Lock()
         self._done: list = []
         self._pending = 0
-        self._thread = None
+        self._threads: list = []
         self._error = None
 
     def wants(self, arcs: int) -> bool:
@@ -166,12 +170,16 @@ class PlainLane:
     def can_solve(self, instance: str) -> bool:
         return self.names is None or instance in self.names
 
+    @property
+    def workers(self) -> int:
+        return len(self.solvers)
+
     def idle(self) -> bool:
         with self._lock:
             return self._pending == 0
 
     def start(self, clock, t0: float, keep_results: bool) -> None:
-        def work():
+        def work(solve):
             while True:
                 r = self._q.get()
                 if r is None:
@@ -183,7 +191,7 @@ class PlainLane:
                         self._pending -= 1
                     continue
                 try:
-                    res = self.solve(r, keep_results)
+                    res = solve(r, keep_results)
                 except Exception as exc:  # surfaced by the serving loop
                     with self._lock:
                         self._error = exc
@@ -196,8 +204,9 @@ class PlainLane:
                     self._done.append(r)
                     self._pending -= 1
 
-        self._thread = threading.Thread(target=work, daemon=True)
-        self._thread.start()
+        self._threads = [threading.Thread(target=work, args=(f,), daemon=True) for f in self.solvers]
+        for t in self._threads:
+            t.start()
 
     def submit(self, r: Request) -> None:
         with self._lock:
@@ -216,10 +225,11 @@ class PlainLane:
         return out
 
     def stop(self) -> None:
-        if self._thread is not None:
+        for _ in self._threads:
             self._q.put(None)
-            self._thread.join()
-            self._thread = None
+        for t in self._threads:
+            t.join()
+        self._threads = []
 
 
 class Server:
@@ -490,36 +500,44 @@ class UploadArena:
         return lo, lo + g.n, g.m
 
 
-def gpu_plain_lane(graphs: dict, big_arcs: int, ordered_sssp: bool = False) -> PlainLane:
+def gpu_plain_lane(graphs: dict, big_arcs: int, ordered_sssp: bool = False, workers: int = 1) -> PlainLane:
     """A PlainLane over resident device graphs (instance name -> DeviceGraph
-    with local node ids): each query runs as one balanced BFS/SSSP solve on
-    a stream of its own.  Instances below big_arcs given here are served by
-    the lane only through a server's idle bypass.  ordered_sssp: SSSP runs
-    on each graph's degree-class ordered copy (built here, once)."""
+    with local node ids): each query runs as one balanced BFS/SSSP solve.
+    workers: solves that may run at once, each worker with a stream, a
+    workspace sized for the largest graph and an output row of its own (the
+    memory a running query holds, reserved up front).  Instances below
+    big_arcs given here are served by the lane only through a server's idle
+    bypass.  ordered_sssp: SSSP runs on each graph's degree-class ordered
+    copy (built here, once)."""
     import torch
 
     from . import lbg
 
     gs = list(graphs.values())
     dev = gs[0].offsets.device
-    stream = torch.cuda.Stream(device=dev)
-    ws = lbg.Workspace(dev)
-    ws.get(max(max(lbg.workspace_bytes(g.n, g.m, "balanced", False),
-                   lbg.workspace_bytes(g.n, g.m, "balanced", True)) for g in gs))
-    out = torch.empty(max(g.n for g in gs), dtype=torch.int32, device=dev)
+    need = max(max(lbg.workspace_bytes(g.n, g.m, "balanced", False),
+                   lbg.workspace_bytes(g.n, g.m, "balanced", True)) for g in gs)
     if ordered_sssp:
         for g in gs:
             g.ensure_ordered()
 
-    def solve(r, keep):
-        g = graphs[r.instance]
-        if r.kind == KIND_BFS:
-            lbg.bfs(g, r.src, out=out[: g.n], workspace=ws, stream=stream)
-        else:
-            lbg.sssp(g, r.src, out=out[: g.n], workspace=ws, stream=stream, ordered=ordered_sssp)
-        if not keep:
-            return None
-        with torch.cuda.stream(stream):
-            return out[: g.n].cpu().numpy()
+    def make_solver():
+        stream = torch.cuda.Stream(device=dev)
+        ws = lbg.Workspace(dev)
+        ws.get(need)
+        out = torch.empty(max(g.n for g in gs), dtype=torch.int32, device=dev)
 
-    return PlainLane(solve, big_arcs, names=graphs.keys())
+        def solve(r, keep):
+            g = graphs[r.instance]
+            if r.kind == KIND_BFS:
+                lbg.bfs(g, r.src, out=out[: g.n], workspace=ws, stream=stream)
+            else:
+                lbg.sssp(g, r.src, out=out[: g.n], workspace=ws, stream=stream, ordered=ordered_sssp)
+            if not keep:
+                return None
+            with torch.cuda.stream(stream):
+                return out[: g.n].cpu().numpy()
+
+        return solve
+
+    return PlainLane([make_solver() for _ in range(max(1, int(workers)))], big_arcs, names=graphs.keys())

@@ -96,7 +96,7 @@ def test_batch_rejects_arc_leaving_instance():
 
 
 def test_graph_launched_batch_replays():
-    """The graph-launched batch (a cached HIP graph of 16 levels, replayed
+    """The graph-launched batch (a cached HIP graph of 64 levels, replayed
     until the batch is done) gives the oracle's rows on every call: reused
     with eager work and synchronisations in between, rebuilt for other
     buffers, and agreeing with the eager batch, including batches longer

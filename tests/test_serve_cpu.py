@@ -1,6 +1,8 @@
 """Serving scheduler on the CPU: admission by slots / rows / upload regions,
 FCFS order, resource reuse, Poisson replay and result identity, with a fake
 engine whose 'kernels' are the CPU oracle (no GPU)."""
+import time
+
 import numpy as np
 import pytest
 
@@ -274,6 +276,39 @@ def test_plain_lane_takes_large_instances():
     assert via_lane and all(r.instance == big for r in via_lane)
     assert all(r.instance != big for r in rep.completed if r.slot >= 0)
     assert all(r.done >= r.admitted for r in rep.completed)  # replay admits ahead of arrival
+
+
+def test_plain_lane_workers_overlap():
+    """A lane with three workers runs queries at once (each worker its own
+    solver), and every result is the oracle's."""
+    import threading
+
+    gs, u, inst = _setup()
+    lock = threading.Lock()
+    running, peak = [0], [0]
+
+    def make(k):
+        def solve(r, keep):
+            with lock:
+                running[0] += 1
+                peak[0] = max(peak[0], running[0])
+            time.sleep(0.01)
+            g = gs[int(r.instance[1:])]
+            res = (O.bfs(g.offsets, g.cols, r.src) if r.kind == serve.KIND_BFS
+                   else O.dijkstra(g.offsets, g.cols, g.weights, r.src).view(np.int32))
+            with lock:
+                running[0] -= 1
+            return res
+        return solve
+
+    lane = serve.PlainLane([make(k) for k in range(3)], big_arcs=0)
+    assert lane.workers == 3
+    eng = FakeEngine(u, max_queries=2, max_rows=6000)
+    reqs = serve.poisson_requests(1e4, 24, inst, seed=17)
+    rep = serve.Server(eng, inst, keep_results=True, plain=lane).run(reqs, replay=True)
+    assert len(rep.completed) == 24 and all(r.slot < 0 for r in rep.completed)
+    _check_results(rep, gs)
+    assert peak[0] >= 2  # queries overlapped
 
 
 def test_plain_lane_error_surfaces():
