@@ -564,7 +564,18 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
     sat = 1.0 / float(np.mean(svc))
     # the plain lane holds every resident instance: large ones always go
     # there, small ones only when the engine and the lane are both idle
-    lane = serve.gpu_plain_lane(singles, big_arcs, ordered_sssp=True, workers=workers)
+    # extra workers start a query only once a queue has built up and its
+    # head has waited longer than the mean plain service time
+    lane = serve.gpu_plain_lane(singles, big_arcs, ordered_sssp=True, workers=workers,
+                                overlap_after=float(np.mean(svc)))
+
+    def by_class(reqs, lat_ms):
+        """p50 / p99 ms per target (resident instance name, or 'upload')."""
+        out = {}
+        for cls in sorted({r.instance or "upload" for r in reqs}):
+            x = np.array([l for r, l in zip(reqs, lat_ms) if (r.instance or "upload") == cls])
+            out[cls] = [round(float(np.percentile(x, 50)), 3), round(float(np.percentile(x, 99)), 3)]
+        return out
 
     def plain_serve(reqs):
         """The same arrivals served FCFS by one plain call per request (upload
@@ -581,7 +592,8 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         lat = np.array(lat) * 1e3
         return {"plain_p50_ms": round(float(np.percentile(lat, 50)), 4),
                 "plain_p99_ms": round(float(np.percentile(lat, 99)), 4),
-                "plain_qps": round(len(reqs) / wall, 2)}
+                "plain_qps": round(len(reqs) / wall, 2),
+                "plain_by_target_p50_p99_ms": by_class(reqs, lat)}
 
     def requests_at(frac):
         return serve.poisson_requests(sat * frac, requests_per_point, inst, upload_graphs=uploads,
@@ -594,6 +606,8 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         rep = serve.Server(eng, inst, upload=arena, plain=lane, idle_bypass=True,
                            levels_per_step=2).run(reqs)
         s = rep.summary()
+        done = sorted(rep.completed, key=lambda r: r.rid)
+        s["by_target_p50_p99_ms"] = by_class(done, [r.latency * 1e3 for r in done])
         s["offered_qps"] = round(sat * frac, 2)
         s["fraction_of_plain_saturation"] = frac
         s.update(plain_serve(reqs))
@@ -609,9 +623,10 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
                        f"U[1,255]) + per-request uploaded uniform graphs n in [2^12, 2^16]; "
                        f"Poisson arrivals, 70% BFS / 30% SSSP, 25% uploads; "
                        f"{requests_per_point} requests per point; gteps counts instance arcs; "
-                       f"instances of >= {big_arcs} arcs are served by a plain lane of {workers} "
+                       f"instances of >= {big_arcs} arcs are served by a plain lane of up to {workers} "
                        f"solves that run at once (each on its own stream and workspace: queries "
-                       f"overlap on the device), the rest are batched by the engine unless the "
+                       f"overlap on the device once a backlog has waited longer than the mean "
+                       f"plain service time), the rest are batched by the engine unless the "
                        f"engine and the lane are both idle (then a resident query runs plain: "
                        f"'bypassed'); plain solves of resident instances run SSSP on their "
                        f"degree-class ordered copy; the engine advances 2 levels per step; "
@@ -750,6 +765,10 @@ def main():
                     help="do not bracket expansion launches with events (no roofline)")
     ap.add_argument("--no-extras", action="store_true",
                     help="plain mode: skip the compact batched and serving measurements")
+    ap.add_argument("--lane-workers", type=int, default=3,
+                    help="serving: plain solves of large resident instances that may run at once")
+    ap.add_argument("--switch-interval-us", type=float, default=0.0,
+                    help="serving: the interpreter's thread switch interval (0 = leave Python's default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, copy a buffer of this many MiB three times "
                          "(a plain copy kernel of known size, to scale rocprofv3 HBM counters)")
@@ -769,6 +788,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.slice_min is not None:
         lbg.set_slice_min(args.slice_min)
+    if args.switch_interval_us > 0:
+        sys.setswitchinterval(args.switch_interval_us * 1e-6)
 
     if args.mode == "batch":
         res = run_batch(lbg, torch, dev, count=256, sources_per_instance=4, hi_exp=18)
@@ -788,7 +809,8 @@ def main():
         return
     if args.mode == "serve":
         res = run_serve(lbg, torch, dev, scales=(20, 22, 24),
-                        fractions=(0.25, 0.5, 0.75, 1.0, 1.25), requests_per_point=2000)
+                        fractions=(0.25, 0.5, 0.75, 1.0, 1.25), requests_per_point=2000,
+                        workers=args.lane_workers)
         p99 = max(p["p99_ms"] for p in res["points"])
         print(json.dumps({"metric": "served p99 latency (ms) over a QPS sweep", "value": p99,
                           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "u32",
@@ -808,7 +830,8 @@ def main():
         torch.cuda.empty_cache()
         log("serving (resident R-MAT 20/22/24 + uploads)")
         out["serving"] = run_serve(lbg, torch, dev, scales=(20, 22, 24), fractions=(0.5, 1.0),
-                                   requests_per_point=400, engine_only_fraction=0.5)
+                                   requests_per_point=400, workers=args.lane_workers,
+                                   engine_only_fraction=0.5)
         torch.cuda.empty_cache()
     if args.cpu_budget > 0:
         log("timing the CPU oracle baseline")

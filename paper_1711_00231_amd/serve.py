@@ -36,7 +36,7 @@ without a GPU.
 from __future__ import annotations
 
 import bisect
-import queue
+from collections import deque
 import threading
 import time
 from dataclasses import dataclass, field
@@ -146,18 +146,25 @@ class PlainLane:
     solve(request, keep) runs the query to completion (the GPU binding
     releases the interpreter lock meanwhile) and returns its result row when
     keep is true.  A sequence of such callables gives one worker thread
-    each (each with its own stream, workspace and output on the GPU): a
-    query that arrives while others run starts as soon as a worker is free,
-    and its work overlaps theirs on the device.  `big_arcs` is the size
-    from which an instance goes here.  names: the resident instances the
-    solvers can serve (None: all); a server with idle_bypass sends small
-    ones here only while everything is idle."""
+    each (each with its own stream, workspace and output on the GPU), so
+    queries can run at once and overlap on the device.  Worker 0 takes the
+    next query whenever it is free; worker k > 0 only while at least k + 1
+    queries are waiting and the first of them has waited overlap_after
+    seconds (a backlog): at light load queries run one at a time, each with
+    the GPU to itself (overlapping them would stretch the longest solves,
+    the latency tail), and they overlap once a queue builds.  `big_arcs` is
+    the size from which an instance goes here.  names: the resident
+    instances the solvers can serve (None: all); a server with idle_bypass
+    sends small ones here only while everything is idle."""
 
-    def __init__(self, solve, big_arcs: int, names=None):
+    def __init__(self, solve, big_arcs: int, names=None, overlap_after: float = 0.0):
+        self.overlap_after = float(overlap_after)
         self.solvers = list(solve) if isinstance(solve, (list, tuple)) else [solve]
         self.big_arcs = int(big_arcs)
         self.names = None if names is None else set(names)
-        self._q: queue.Queue = queue.Queue()
+        self._q: deque = deque()
+        self._cv = threading.Condition()
+        self._stopping = False
         self._lock = threading.Lock()
         self._done: list = []
         self._pending = 0
@@ -178,10 +185,29 @@ class PlainLane:
         with self._lock:
             return self._pending == 0
 
-    def start(self, clock, t0: float, keep_results: bool) -> None:
-        def work(solve):
+    def _take(self, k: int, clock, t0: float):
+        """The next query for worker k, once it may take one; None to stop."""
+        with self._cv:
             while True:
-                r = self._q.get()
+                if self._stopping and not self._q:
+                    return None
+                wait = None
+                if self._q:
+                    if k == 0 or self._stopping:
+                        return self._q.popleft()
+                    if len(self._q) >= k + 1:
+                        waited = clock() - t0 - self._q[0].arrival
+                        if waited >= self.overlap_after:
+                            return self._q.popleft()
+                        wait = self.overlap_after - waited
+                self._cv.wait(wait)
+
+    def start(self, clock, t0: float, keep_results: bool) -> None:
+        self._stopping = False
+
+        def work(k, solve):
+            while True:
+                r = self._take(k, clock, t0)
                 if r is None:
                     return
                 if r.status == "cancelled":  # withdrawn while queued here
@@ -204,14 +230,17 @@ class PlainLane:
                     self._done.append(r)
                     self._pending -= 1
 
-        self._threads = [threading.Thread(target=work, args=(f,), daemon=True) for f in self.solvers]
+        self._threads = [threading.Thread(target=work, args=(k, f), daemon=True)
+                         for k, f in enumerate(self.solvers)]
         for t in self._threads:
             t.start()
 
     def submit(self, r: Request) -> None:
         with self._lock:
             self._pending += 1
-        self._q.put(r)
+        with self._cv:
+            self._q.append(r)
+            self._cv.notify_all()
 
     def busy(self) -> bool:
         with self._lock:
@@ -225,8 +254,9 @@ class PlainLane:
         return out
 
     def stop(self) -> None:
-        for _ in self._threads:
-            self._q.put(None)
+        with self._cv:
+            self._stopping = True
+            self._cv.notify_all()
         for t in self._threads:
             t.join()
         self._threads = []
@@ -500,7 +530,8 @@ class UploadArena:
         return lo, lo + g.n, g.m
 
 
-def gpu_plain_lane(graphs: dict, big_arcs: int, ordered_sssp: bool = False, workers: int = 1) -> PlainLane:
+def gpu_plain_lane(graphs: dict, big_arcs: int, ordered_sssp: bool = False, workers: int = 1,
+                   overlap_after: float = 0.0) -> PlainLane:
     """A PlainLane over resident device graphs (instance name -> DeviceGraph
     with local node ids): each query runs as one balanced BFS/SSSP solve.
     workers: solves that may run at once, each worker with a stream, a
@@ -540,4 +571,5 @@ def gpu_plain_lane(graphs: dict, big_arcs: int, ordered_sssp: bool = False, work
 
         return solve
 
-    return PlainLane([make_solver() for _ in range(max(1, int(workers)))], big_arcs, names=graphs.keys())
+    return PlainLane([make_solver() for _ in range(max(1, int(workers)))], big_arcs, names=graphs.keys(),
+                     overlap_after=overlap_after)

@@ -311,6 +311,36 @@ def test_plain_lane_workers_overlap():
     assert peak[0] >= 2  # queries overlapped
 
 
+def test_plain_lane_extra_workers_wait_for_a_backlog():
+    """Spaced arrivals (each solve ends before the next request arrives)
+    never build a queue, so the lane's extra workers never start one: the
+    queries run one at a time, as in a plain FCFS queue."""
+    import threading
+
+    gs, u, inst = _setup()
+    lock = threading.Lock()
+    running, peak = [0], [0]
+
+    def make(k):
+        def solve(r, keep):
+            with lock:
+                running[0] += 1
+                peak[0] = max(peak[0], running[0])
+            time.sleep(0.005)
+            with lock:
+                running[0] -= 1
+            return None
+        return solve
+
+    lane = serve.PlainLane([make(k) for k in range(3)], big_arcs=0)
+    eng = FakeEngine(u, max_queries=2, max_rows=6000)
+    reqs = serve.poisson_requests(1e4, 8, inst, seed=19)
+    for i, r in enumerate(reqs):
+        r.arrival = 0.05 * i
+    rep = serve.Server(eng, inst, plain=lane).run(reqs)
+    assert len(rep.completed) == 8 and peak[0] == 1
+
+
 def test_plain_lane_error_surfaces():
     gs, u, inst = _setup()
 
