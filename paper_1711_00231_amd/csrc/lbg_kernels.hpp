@@ -175,6 +175,90 @@ __device__ __forceinline__ bool relax(const KArgs& a, uint32_t L, int32_t v, uin
   return *d > 0;  // a node without out-arcs has nothing to expand
 }
 
+// relax() for kB arcs of one lane at once: each step (filter reads, claims
+// or atomic minima, the winners' offsets) is issued for all kB arcs before
+// any result is used, so a lane keeps kB requests in flight instead of one.
+// v[b] < 0: no arc.  On return want[b] says whether v[b] joins the next
+// worklist, with its first arc s[b] and out-degree d[b].
+template <bool kSssp, int kB>
+__device__ __forceinline__ void relax_batch(const KArgs& a, uint32_t L, int32_t (&v)[kB], const uint32_t (&du)[kB],
+                                            const uint32_t (&w)[kB], uint32_t* upd, uint32_t* atom,
+                                            int32_t (&s)[kB], int32_t (&d)[kB], bool (&want)[kB]) {
+  bool bad = false;
+#pragma unroll
+  for (int b = 0; b < kB; ++b)
+    if (v[b] >= 0 && static_cast<uint32_t>(v[b]) >= a.n) {  // malformed cols (see lbg_validate_csr)
+      bad = true;
+      v[b] = -1;
+    }
+  if (bad) atomicOr(&a.ctl->error, kErrBadArc);
+  uint32_t x[kB];
+  bool win[kB];
+  if (!kSssp) {
+    uint32_t* f = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;  // holds `seen`
+#pragma unroll
+    for (int b = 0; b < kB; ++b) x[b] = v[b] >= 0 ? f[static_cast<uint32_t>(v[b]) >> 5] : ~0u;
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const uint32_t word = static_cast<uint32_t>(v[b]) >> 5, bit = 1u << (v[b] & 31);
+      if (v[b] >= 0 && !(x[b] & bit)) {
+        f[word] = x[b] | bit;  // plain store; a lost bit only costs one more atomic
+        ++*atom;
+        x[b] = atomicOr(&a.visited[word], bit);
+      } else {
+        x[b] = ~0u;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const uint32_t word = static_cast<uint32_t>(v[b]) >> 5, bit = 1u << (v[b] & 31);
+      win[b] = v[b] >= 0 && !(x[b] & bit);
+      if (win[b]) {
+        a.levels[v[b]] = static_cast<int32_t>(L + 1);
+        a.seen[(L + 1) & 1][word] |= bit;  // plain read-modify-write: a lost bit only costs an atomic later
+        ++*upd;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < kB; ++b) x[b] = v[b] >= 0 ? f16_bound(a.d16[v[b]]) : 0u;
+    unsigned long long old[kB];
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const uint32_t alt = du[b] + w[b];
+      old[b] = 0ull;
+      if (v[b] >= 0 && alt < x[b]) {
+        ++*atom;
+        old[b] = atomicMin(&a.dstate[v[b]], (static_cast<unsigned long long>(alt) << 32) | (L + 1));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const uint32_t alt = du[b] + w[b];
+      const bool better = v[b] >= 0 && alt < x[b] && alt < static_cast<uint32_t>(old[b] >> 32);
+      if (better) {
+        a.d16[v[b]] = f16_of(alt);  // filter; may lag the state, never undercuts it
+        ++*upd;
+      }
+      win[b] = better && static_cast<uint32_t>(old[b]) != L + 1;  // not yet queued this iteration
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kB; ++b) {
+    s[b] = 0;
+    d[b] = 0;
+    if (win[b]) {
+      s[b] = a.offsets[v[b]];
+      d[b] = a.offsets[v[b] + 1];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kB; ++b) {
+    d[b] -= s[b];
+    want[b] = win[b] && d[b] > 0;  // a node without out-arcs has nothing to expand
+  }
+}
+
 // ------------------------------------------------------------------ init --
 // Output = infinity, source = 0, visited/stamp cleared, worklist 0 = {src}
 // (node strategies) or src's arcs (edge strategy).
@@ -1197,23 +1281,35 @@ __global__ __launch_bounds__(kBlock) void k_expand_binned(KArgs a, uint32_t L) {
   auto flush = [&]() { q.flush_split(a, nxt, nctr); };
   uint32_t upd = 0, atom = 0;
 
-  // relax the arcs [s + k0, s + len) of one entry, k0 + stride*j per lane
+  // relax the arcs [s + k0, s + len) of one entry, k0 + stride*j per lane,
+  // kBinB of a lane's arcs at a time (relax_batch); `rounds` is uniform over
+  // the lanes that share the entry (wave or workgroup)
+  constexpr int kBinB = kSssp ? 4 : 8;  // SSSP: fewer registers per arc in flight (measured)
   auto expand = [&](bool act, uint32_t s, uint32_t len, uint32_t du, uint32_t k0, uint32_t stride,
                     uint32_t rounds) {
-    for (uint32_t j = 0; j < rounds; ++j) {
-      const uint32_t k = k0 + j * stride;
-      int32_t v = -1, ns = 0, nd = 0;
-      bool want = false;
-      if (act && k < len) {
-        const uint32_t e = s + k;
-        if (e < a.m) {
-          v = a.cols[e];
-          want = relax<kSssp>(a, L, v, du, kSssp ? a.weights[e] : 0u, &upd, &atom, &ns, &nd);
-        } else {
-          atomicOr(&a.ctl->error, kErrBadArc);
+    for (uint32_t j0 = 0; j0 < rounds; j0 += kBinB) {
+      int32_t v[kBinB], ns[kBinB], nd[kBinB];
+      uint32_t w[kBinB], dd[kBinB];
+      bool want[kBinB];
+#pragma unroll
+      for (int b = 0; b < kBinB; ++b) {
+        const uint32_t k = k0 + (j0 + b) * stride;
+        v[b] = -1;
+        w[b] = 0;
+        dd[b] = du;
+        if (act && j0 + b < rounds && k < len) {
+          const uint32_t e = s + k;
+          if (e < a.m) {
+            v[b] = a.cols[e];
+            if (kSssp) w[b] = a.weights[e];
+          } else {
+            atomicOr(&a.ctl->error, kErrBadArc);
+          }
         }
       }
-      q.push(want, ns, nd, v, flush);
+      relax_batch<kSssp, kBinB>(a, L, v, dd, w, &upd, &atom, ns, nd, want);
+#pragma unroll
+      for (int b = 0; b < kBinB; ++b) q.push(want[b], ns[b], nd[b], v[b], flush);
     }
   };
 
@@ -1374,7 +1470,27 @@ __global__ __launch_bounds__(kBlock) void k_expand_hier(KArgs a, uint32_t L, uin
       const unsigned long long hi = (w0 + mdt) < deg ? (w0 + mdt) : deg;
       const uint32_t len = static_cast<uint32_t>(hi - lo);
       const uint32_t rounds = static_cast<uint32_t>(wave_max(static_cast<int32_t>(len)));
-      for (uint32_t k = 0; k < rounds; ++k) relax_push(k < len, st + static_cast<uint32_t>(lo) + k, du);
+      // the window's arcs, kHierB of this thread's at a time (relax_batch)
+      constexpr int kHierB = kSssp ? 4 : 8;
+      for (uint32_t k0 = 0; k0 < rounds; k0 += kHierB) {
+        int32_t v[kHierB], ns[kHierB], nd[kHierB];
+        uint32_t w[kHierB], dd[kHierB];
+        bool want[kHierB];
+#pragma unroll
+        for (int b = 0; b < kHierB; ++b) {
+          v[b] = -1;
+          w[b] = 0;
+          dd[b] = du;
+          if (k0 + b < len) {
+            const uint32_t arc = st + static_cast<uint32_t>(lo) + k0 + b;
+            v[b] = a.cols[arc];
+            if (kSssp) w[b] = a.weights[arc];
+          }
+        }
+        relax_batch<kSssp, kHierB>(a, L, v, dd, w, &upd, &atom, ns, nd, want);
+#pragma unroll
+        for (int b = 0; b < kHierB; ++b) q.push(want[b], ns[b], nd[b], v[b], flush);
+      }
       // arcs beyond the window: the node stays active
       const bool more = i < cnt && deg > w0 + mdt;
       const uint64_t mask = __ballot(more);
