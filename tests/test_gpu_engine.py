@@ -126,15 +126,18 @@ def test_server_loop_on_gpu_with_uploads():
 
 def test_server_at_stated_scales():
     """Serving at the stated sizes: resident R-MAT scale 20 (31 M arcs,
-    continuously batched by the engine) and scale 22 (128 M arcs, served by
-    plain solves on the second stream, SSSP on its ordered copy) plus
-    per-request uploaded uniform graphs with n in [2^12, 2^16]; a Poisson
-    trace of mixed BFS/SSSP (70/30) on wall-clock arrivals.  Every result is
-    checked: the oracle's full vector for scale 20 and the uploads, the
-    oracle's O(m) exactness certificate for scale 22."""
+    continuously batched by the engine), scales 22 and 24 (128 M and 521 M
+    arcs, served by a lane of three plain solves that overlap on the device,
+    SSSP on the ordered copies) plus per-request uploaded uniform graphs with
+    n in [2^12, 2^16]; a Poisson trace of mixed BFS/SSSP (70/30) on
+    wall-clock arrivals, fast enough that a backlog builds and lane solves
+    overlap.  Every result is checked: the oracle's full vector for scale 20
+    and the uploads, the oracle's O(m) exactness certificate for scales 22
+    and 24."""
     import graphgen as gg
 
-    r20, r22 = gg.rmat(20, salt=70), gg.rmat(22, salt=72)
+    r20, r22, r24 = gg.rmat(20, salt=70), gg.rmat(22, salt=72), gg.rmat(24, salt=74)
+    big = {"rmat22": r22, "rmat24": r24}
     uploads = [gg.uniform(n=int(2 ** e), k=8, wlo=1, whi=255, salt=60 + i)
                for i, e in enumerate(np.linspace(12, 16, 4))]
     u, nb, eb = gg.pack([r20])
@@ -144,26 +147,30 @@ def test_server_at_stated_scales():
     dg = lbg.DeviceGraph.from_numpy(off, np.concatenate([u.cols, cols_e]), np.concatenate([u.weights, w_e]))
     del off, off_e, cols_e, w_e
     arena = serve.UploadArena(dg, u.n, u.m, R, NC, MC)
-    inst = {"rmat20": serve.Instance(0, r20.n, r20.m), "rmat22": serve.Instance(0, r22.n, r22.m)}
-    srcs = {"rmat20": gg.sources(r20, 64, gg.FAMILY_SERVE, salt=20),
-            "rmat22": gg.sources(r22, 64, gg.FAMILY_SERVE, salt=22)}
+    inst = {"rmat20": serve.Instance(0, r20.n, r20.m)}
+    inst.update({nm: serve.Instance(0, g.n, g.m) for nm, g in big.items()})
+    srcs = {"rmat20": gg.sources(r20, 64, gg.FAMILY_SERVE, salt=20)}
+    srcs.update({nm: gg.sources(g, 64, gg.FAMILY_SERVE, salt=int(nm[4:])) for nm, g in big.items()})
     eng = lbg.Engine(dg, max_queries=16, max_rows=6 * r20.n + 4 * NC,
                      max_level_arcs=min(2**32 - 1, 8 * (u.m + R * MC)))
-    lane = serve.gpu_plain_lane({"rmat22": lbg.DeviceGraph.from_numpy(r22.offsets, r22.cols, r22.weights)},
-                                big_arcs=r22.m, ordered_sssp=True)
-    reqs = serve.poisson_requests(400.0, 36, inst, upload_graphs=uploads, upload_share=0.25, seed=5,
+    lane = serve.gpu_plain_lane({nm: lbg.DeviceGraph.from_numpy(g.offsets, g.cols, g.weights)
+                                 for nm, g in big.items()}, big_arcs=r22.m, ordered_sssp=True, workers=3)
+    assert lane.workers == 3
+    reqs = serve.poisson_requests(600.0, 40, inst, upload_graphs=uploads, upload_share=0.25, seed=5,
                                   sources=srcs)
     rep = serve.Server(eng, inst, upload=arena, keep_results=True, plain=lane, levels_per_step=2).run(reqs)
     eng.close()
-    assert len(rep.completed) == 36 and not rep.dropped
-    seen = {"rmat20": 0, "rmat22": 0, None: 0}
+    assert len(rep.completed) == 40 and not rep.dropped
+    seen = {"rmat20": 0, "rmat22": 0, "rmat24": 0, None: 0}
     for r in rep.completed:
         seen[r.instance] += 1
-        if r.instance == "rmat22":
+        print(f"checking request {r.rid} on {r.instance or 'upload'} kind {r.kind}", flush=True)
+        if r.instance in big:
+            g = big[r.instance]
             assert r.slot < 0  # the plain lane
-            w = None if r.kind == lbg.KIND_BFS else r22.weights
+            w = None if r.kind == lbg.KIND_BFS else g.weights
             d = r.result if w is None else r.result.view(np.uint32)
-            assert O.certificate(r22.offsets, r22.cols, w, r.src, d)[0] == 0, r.rid
+            assert O.certificate(g.offsets, g.cols, w, r.src, d)[0] == 0, r.rid
         else:
             g = r20 if r.instance == "rmat20" else r.graph
             assert np.array_equal(r.result, _expected(g, r.src, r.kind)), r.rid
