@@ -402,6 +402,29 @@ def run_strategies(lbg, torch, g, srcs, dev):
         out[name] = {"sssp_ms": [round(x * 1e3, 3) for x in ts], "sssp_gteps": round(arcs / sum(ts) / 1e9, 3)}
         log(f"strategy {name}: {out[name]}")
 
+    # hierarchical processing with a fixed window (MDT 256, the binned
+    # strategy's tuned split size) beside the histogram rule's
+    lbg.set_hier_mdt(256)
+    try:
+        res = {}
+        for kind, f in (("bfs", lbg.bfs), ("sssp", lbg.sssp)):
+            ts, arcs = [], 0
+            for s in srcs[:2]:
+                lv = lbg.bfs(dg, int(s), strategy="balanced", workspace=ws).cpu().numpy()
+                arcs += int(deg[lv != lbg.BFS_INF].sum())
+                f(dg, int(s), strategy="hier", workspace=ws)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                f(dg, int(s), strategy="hier", workspace=ws)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            res[f"{kind}_ms"] = [round(x * 1e3, 3) for x in ts]
+            res[f"{kind}_gteps"] = round(arcs / sum(ts) / 1e9, 3)
+        out["hier_mdt256"] = res
+        log(f"strategy hier_mdt256: {res}")
+    finally:
+        lbg.set_hier_mdt(0)
+
     # balanced SSSP on packed 32-bit arcs (one load per arc), when ids and
     # weights fit in 32 bits, and on the degree-class ordered copy
     try:

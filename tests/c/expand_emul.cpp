@@ -322,6 +322,7 @@ struct Solver {
           }
           for (uint32_t l = 0; l < T / 32; ++l) flag[l] = 0u;
           // staging
+          bool live = false;
           for (uint32_t j0 = 0; j0 < T; j0 += 64) {
             bool anyv = false;
             for (uint32_t lane = 0; lane < 64; ++lane) {
@@ -339,6 +340,7 @@ struct Solver {
                   if (row < g.n) {
                     const unsigned long long sv = dstate[row];
                     du[j] = static_cast<uint32_t>(sv) == L + 1 ? kSsspInf : static_cast<uint32_t>(sv >> 32);
+                    live = live || static_cast<uint32_t>(sv) != L + 1;
                   } else {
                     du[j] = kSsspInf;
                     error |= 8u;
@@ -350,13 +352,21 @@ struct Solver {
             }
             if (!anyv) break;
           }
+          // SSSP: a tile whose staged entries were all improved again ends here
+          if (kSssp && !live && !(error & 8u)) continue;
+          uint32_t nent = 0;
           {
             uint32_t acc = 0;
             for (uint32_t l = 0; l < T / 32; ++l) {
               wpre[l] = acc;
               acc += popc(flag[l]);
             }
+            nent = acc;
           }
+          // a tile inside one entry maps every slot to entry 0
+          const bool single = nent == 1u;
+          if (single && base_tile[0] != cur_tile_id) ++R->stale_lds;
+          const uint32_t b0 = single ? base[0] : 0u, d0 = (single && kSssp) ? du[0] : 0u;
           // phase A
           std::vector<int32_t> vv(kItems * 64, -1);
           std::vector<uint32_t> ww(kItems * 64, 0), dd(kItems * 64, 0);
@@ -364,17 +374,24 @@ struct Solver {
             for (uint32_t lane = 0; lane < 64; ++lane) {
               const uint32_t s = r * 64 + lane, q = r * 64 + lane;
               if (t0 + s >= t1) continue;
-              const uint32_t k = s >> 5;
-              const uint32_t msk = static_cast<uint32_t>((2ull << (s & 31)) - 1ull);
-              const int slot = static_cast<int>(wpre[k] + popc(flag[k] & msk)) - 1;
-              if (slot >= 0 && base_tile[static_cast<uint32_t>(slot) % T] != cur_tile_id) ++R->stale_lds;
-              const uint32_t e = slot >= 0 ? base[static_cast<uint32_t>(slot)] + s : g.m;
-              if (kSssp && slot >= 0 && du[static_cast<uint32_t>(slot)] == kSsspInf) {
+              int slot = 0;
+              uint32_t e, dslot = d0;
+              if (single) {
+                e = b0 + s;
+              } else {
+                const uint32_t k = s >> 5;
+                const uint32_t msk = static_cast<uint32_t>((2ull << (s & 31)) - 1ull);
+                slot = static_cast<int>(wpre[k] + popc(flag[k] & msk)) - 1;
+                if (slot >= 0 && base_tile[static_cast<uint32_t>(slot) % T] != cur_tile_id) ++R->stale_lds;
+                e = slot >= 0 ? base[static_cast<uint32_t>(slot)] + s : g.m;
+                if (kSssp && slot >= 0) dslot = du[static_cast<uint32_t>(slot)];
+              }
+              if (kSssp && slot >= 0 && dslot == kSsspInf) {
                 // skipped entry
               } else if (e < g.m) {
                 vv[q] = (*g.cols)[e];
                 if (kSssp) {
-                  dd[q] = du[static_cast<uint32_t>(slot)];
+                  dd[q] = dslot;
                   ww[q] = (*g.weights)[e];
                 }
               } else {
