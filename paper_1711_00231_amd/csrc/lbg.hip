@@ -681,7 +681,7 @@ dim3 row_grid(int64_t queries, int64_t max_len) {
 
 // ----------------------------------------------------------------- batch --
 struct BatchLayout {
-  size_t ctl, qtab, dstate, rbits, node[2], qid[2], eprefix[2], estart[2], tile[2], total;
+  size_t ctl, qtab, dstate, rbits, d16, node[2], qid[2], eprefix[2], estart[2], tile[2], total;
   uint32_t node_cap, tile_cap;
 };
 
@@ -697,6 +697,7 @@ BatchLayout batch_layout(int32_t num_queries, int64_t rows, int64_t total_arcs) 
   L.qtab = take(sizeof(lbg::QInfo) * static_cast<size_t>(num_queries));
   L.dstate = take(sizeof(unsigned long long) * static_cast<size_t>(rows));
   L.rbits = take(sizeof(uint32_t) * ((static_cast<size_t>(rows) + 31) / 32));  // BFS rows
+  L.d16 = take(sizeof(uint16_t) * static_cast<size_t>(rows));  // filter of SSSP rows
   L.node_cap = static_cast<uint32_t>(rows);
   L.tile_cap = static_cast<uint32_t>((total_arcs + lbg::kMultiTile - 1) / lbg::kMultiTile + 2);
   for (int b = 0; b < 2; ++b) {
@@ -837,6 +838,7 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
   a.dist = out;
   a.dstate = reinterpret_cast<unsigned long long*>(ws + Lay.dstate);
   a.visited = reinterpret_cast<uint32_t*>(ws + Lay.rbits);
+  a.d16 = reinterpret_cast<uint16_t*>(ws + Lay.d16);
   for (int b = 0; b < 2; ++b) {
     a.fr[b].node = reinterpret_cast<int32_t*>(ws + Lay.node[b]);
     a.fr[b].qid = reinterpret_cast<int32_t*>(ws + Lay.qid[b]);
@@ -1067,6 +1069,7 @@ int lbg_engine_create(const int32_t* offsets, const int32_t* cols, const uint32_
   a.dist = rows_out;
   a.dstate = reinterpret_cast<unsigned long long*>(e->ws + Lay.dstate);
   a.visited = reinterpret_cast<uint32_t*>(e->ws + Lay.rbits);
+  a.d16 = reinterpret_cast<uint16_t*>(e->ws + Lay.d16);
   for (int b = 0; b < 2; ++b) {
     a.fr[b].node = reinterpret_cast<int32_t*>(e->ws + Lay.node[b]);
     a.fr[b].qid = reinterpret_cast<int32_t*>(e->ws + Lay.qid[b]);

@@ -96,7 +96,7 @@ struct KArgs {
   uint32_t* seen[2];     // BFS: read-only-per-level snapshots of `visited` (double-buffered)
   uint32_t* xfilter;     // BFS: per-XCD advisory copy of `visited`, kXcds x words
   unsigned long long* dstate;  // SSSP: (distance << 32) | iteration of last improvement
-  uint16_t* d16;         // SSSP single solves: filter, min(an upper bound of the distance, 0xffff)
+  uint16_t* d16;         // SSSP filter per node (batched: per row), min(an upper bound of the distance, 0xffff)
   // Packed arcs (SSSP, balanced): arc e = (cols[e] << wbits) | weights[e],
   // one 32-bit load per arc instead of two.
   const uint32_t* arcs;

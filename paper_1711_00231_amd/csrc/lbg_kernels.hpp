@@ -29,9 +29,12 @@
 //    quarter of the random-read footprint: 8 MiB at scale 22, half of what an
 //    XCD's L2 holds); winners refresh it with plain stores, so it may lag the
 //    state but never undercuts it, and 0xffff (too large, or unknown) never
-//    filters.  Batched rows filter on their 4-byte output row instead.  A
-//    frontier node's own distance is always read from the state, and the
-//    epilogue writes the output from the state.
+//    filters.  Batched SSSP rows keep the same 2-byte copy per row: their
+//    state is far larger than the last-level cache, and the copy halves the
+//    random-read footprint of filtering on the 4-byte output row (measured:
+//    3.5 % faster on 2,048 solves over 322 M arcs).  A frontier node's own
+//    distance is always read from the state, and the epilogue writes the
+//    output from the state.
 // Plain reads may be stale inside a launch; values only move one way (bits
 // set, distances decrease), so a stale read can only cost an extra atomic,
 // never a missed update.
@@ -509,7 +512,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   uint32_t* fx = a.xfilter + static_cast<size_t>(blockIdx.x % kXcds) * a.words;
   uint32_t* seen_nxt = a.seen[(L + 1) & 1];
   // A frontier node's own distance comes from the packed state
-  // (authoritative); the per-arc filter reads the output array.
+  // (authoritative); the per-arc filter reads the 2-byte copy.
   const uint32_t state_len = kMulti ? a.rows : a.n;
   uint32_t upd = 0, atom = 0, qcount = 0, skip = 0;
   if (!kSssp) refresh_seen(a, L);
@@ -562,6 +565,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
               // BFS query: its frontier nodes are exactly its nodes at hop
               // distance L - level0
               w.du[j] = L - level0;
+              live = true;
               if (row >= state_len) {
                 w.du[j] = kSsspInf;
                 bad = true;
@@ -587,7 +591,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
       if (!__any(valid)) break;
     }
     wave_sync();
-    if (kSssp && !kMulti && !__any(live) && !__any(bad)) {
+    if (kSssp && !__any(live) && !__any(bad)) {
       // every entry of the tile improved again this iteration (a hub queued
       // for the next one, typically): nothing to load, the tile ends here
       skip += (t1 - t0 + 63u - lane) / 64u;  // this lane's share of the tile's slots
@@ -603,8 +607,9 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
     }
     wave_sync();
     // a tile inside one entry (a hub's arcs): every slot maps to entry 0,
-    // with no per-slot lookups (measured: SSSP 11 % faster on R-MAT 22)
-    const bool single = !kMulti && nent == 1u;
+    // with no per-slot lookups (measured: SSSP 11 % faster on R-MAT 22;
+    // batched solves 1 % faster with this and the skipped-tile exit)
+    const bool single = nent == 1u;
     uint32_t b0 = 0, d0 = 0;
     if (single) {
       b0 = w.base[0];
@@ -721,9 +726,8 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
       for (int r = 0; r < kItems; ++r) {
         cd[r] = 0u;
         if (vv[r] >= 0) {
-          if (!kMulti) cd[r] = f16_bound(*at<kNarrow>(static_cast<const uint16_t*>(a.d16), row[r]));
-          else if (bfsq[kMulti ? r : 0]) cd[r] = *at<kNarrow>(static_cast<const uint32_t*>(a.visited), row[r] >> 5);
-          else cd[r] = *at<kNarrow>(static_cast<const uint32_t*>(a.dist), row[r]);
+          if (kMulti && bfsq[kMulti ? r : 0]) cd[r] = *at<kNarrow>(static_cast<const uint32_t*>(a.visited), row[r] >> 5);
+          else cd[r] = f16_bound(*at<kNarrow>(static_cast<const uint16_t*>(a.d16), row[r]));
         }
       }
       unsigned long long old[kItems];
@@ -776,10 +780,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
           push[r] = won;
         } else {
           const bool better = vv[r] >= 0 && alt < static_cast<uint32_t>(old[r] >> 32);
-          if (better) {  // filter (see top of file)
-            if (kMulti) *at<kNarrow>(a.dist, row[r]) = alt;
-            else *at<kNarrow>(a.d16, row[r]) = f16_of(alt);
-          }
+          if (better) *at<kNarrow>(a.d16, row[r]) = f16_of(alt);  // filter (see top of file)
           upd += better ? 1u : 0u;
           push[r] = better && static_cast<uint32_t>(old[r]) != L + 1;
         }
@@ -1663,7 +1664,10 @@ __device__ __forceinline__ void fill_chunk(const KArgs& a, const QInfo& qi, uint
   const uint32_t r0 = static_cast<uint32_t>(qi.row_start) + c0;
   const uint32_t r1 = static_cast<uint32_t>(qi.row_start) + min(static_cast<uint32_t>(qi.row_len), c0 + kRowChunk);
   for (uint32_t idx = r0 + threadIdx.x; idx < r1; idx += kBlock) {
-    if (qi.kind) a.dstate[idx] = static_cast<unsigned long long>(kSsspInf) << 32;
+    if (qi.kind) {
+      a.dstate[idx] = static_cast<unsigned long long>(kSsspInf) << 32;
+      a.d16[idx] = static_cast<uint16_t>(kF16None);
+    }
     a.dist[idx] = kSsspInf;
   }
   if (!qi.kind) {
@@ -1689,8 +1693,10 @@ __device__ __forceinline__ void finish_chunk(const KArgs& a, const QInfo& qi, ui
 
 __device__ __forceinline__ void seed_row(const KArgs& a, const QInfo& qi) {
   const uint32_t row = static_cast<uint32_t>(qi.src + qi.delta);
-  if (qi.kind) a.dstate[row] = 0ull;
-  else atomicOr(&a.visited[row >> 5], 1u << (row & 31));
+  if (qi.kind) {
+    a.dstate[row] = 0ull;
+    a.d16[row] = 0;
+  } else atomicOr(&a.visited[row >> 5], 1u << (row & 31));
   a.dist[row] = 0u;
 }
 

@@ -158,7 +158,7 @@ def test_batch_workspace_and_argument_errors():
     al = lambda x: (x + 255) // 256 * 256
     Q, rows, arcs = 7, 5000, 123457
     tiles = (arcs + T - 1) // T + 2
-    exp = (al(128 + 8 * 128) + al(32 * Q) + al(8 * rows) + al(4 * ((rows + 31) // 32))
+    exp = (al(128 + 8 * 128) + al(32 * Q) + al(8 * rows) + al(4 * ((rows + 31) // 32)) + al(2 * rows)
            + 2 * (4 * al(4 * rows) + al(4 * tiles)))
     assert lbgmod.batch_workspace_bytes(Q, rows, arcs) == exp
     assert lbgmod.batch_workspace_bytes(0, rows, arcs) == 0
