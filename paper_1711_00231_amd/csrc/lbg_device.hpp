@@ -64,7 +64,8 @@ struct Ctl {
   // [x][0] updates, [x][1] global atomics issued; [x][2], [x][3] the same for
   // levels run by the small-frontier kernel; [x][4 + L % 3] the packed tail
   // (nodes << 32 | edges) of slice x's worklist of level L (destination-
-  // sliced strategy)
+  // sliced strategy); [x][8 + L % 3] the balanced kernel's tile counter of
+  // XCD x for level L (single solves)
   unsigned long long xstat[kXcds][16];
 };
 static_assert(sizeof(Ctl) == 128 + kXcds * 128, "Ctl layout");

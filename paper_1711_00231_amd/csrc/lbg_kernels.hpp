@@ -519,15 +519,46 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
 
   const uint32_t ntiles = (Ef + T - 1) / T;
   const uint32_t W = gridDim.x * kWaves;
+  // Tile deal.  Tiles [0, S) go round-robin to the W wavefronts (tile g,
+  // g + W, ...); single solves take the last eighth from per-XCD counters
+  // (XCD x hands out S + x, S + x + 8, ...), so a wavefront that drew cheap
+  // tiles (skipped entries, few winners) takes more at the end instead of
+  // waiting at the workgroup's final barrier for its slowest sibling.  A
+  // larger dynamic share loses: hundreds of wavefronts then queue on each
+  // counter (measured on R-MAT 22: an eighth dynamic, BFS 2 % and SSSP 2.4 %
+  // faster than all round-robin; a quarter 1 %; half or all, SSSP 4-11 %
+  // slower).  The first round is always round-robin, so levels of at most
+  // W tiles take no atomic.  The counters of level L are
+  // ctl->xstat[x][8 + L % 3], cleared by launch L - 1 (or by the
+  // small-frontier kernel that ran level L - 1, or by k_init).
+  const bool dyn = !kMulti && gridDim.x >= static_cast<uint32_t>(kXcds);
+  const uint32_t S = (dyn && ntiles > W) ? max(W, (ntiles - ntiles / 8) / W * W) : ntiles;
+  const uint32_t xcd = blockIdx.x % kXcds;
+  unsigned long long* const dctr = &a.ctl->xstat[xcd][8 + L % 3];
+  if (dyn && blockIdx.x < static_cast<uint32_t>(kXcds) && threadIdx.x == 0)
+    a.ctl->xstat[blockIdx.x][8 + (L + 1) % 3] = 0ull;
+  auto take = [&]() -> uint32_t {  // wave-uniform
+    uint32_t k = 0;
+    if (lane == 0) k = static_cast<uint32_t>(atomicAdd(dctr, 1ull));
+    k = __shfl(k, 0, 64);
+    return S + xcd + static_cast<uint32_t>(kXcds) * k;
+  };
   uint32_t tile = blockIdx.x * kWaves + wid;
+  if (tile >= S) tile = S < ntiles ? take() : ntiles;
   uint32_t i0_next = tile < ntiles ? static_cast<uint32_t>(*at<kNarrow>(cur.tile_node, tile)) : 0u;
-  for (; tile < ntiles; tile += W) {
+  uint32_t tnext = ntiles;
+  for (; tile < ntiles; tile = tnext) {
     const uint32_t i0 = i0_next;
-    if (tile + W < ntiles) i0_next = static_cast<uint32_t>(*at<kNarrow>(cur.tile_node, tile + W));
+    // next tile: its mark is fetched now (round-robin) or once the counter
+    // has answered, after staging (dynamic)
+    const bool rr = tile + W < S;
+    tnext = rr ? tile + W : (S < ntiles ? take() : ntiles);
+    if (rr) i0_next = static_cast<uint32_t>(*at<kNarrow>(cur.tile_node, tnext));
     const uint32_t t0 = tile * T;
     const uint32_t t1 = min(t0 + T, Ef);
     if (i0 >= nf) {  // wave-uniform; cannot happen when every tile was marked
       if (lane == 0) atomicOr(&a.ctl->error, kErrBadTile);
+      if (!rr && tnext < ntiles) i0_next = static_cast<uint32_t>(*at<kNarrow>(cur.tile_node, tnext));
       continue;
     }
     if (lane < T / 32) w.flag[lane] = 0u;
@@ -590,6 +621,7 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
       }
       if (!__any(valid)) break;
     }
+    if (!rr && tnext < ntiles) i0_next = static_cast<uint32_t>(*at<kNarrow>(cur.tile_node, tnext));
     wave_sync();
     if (kSssp && !__any(live) && !__any(bad)) {
       // every entry of the tile improved again this iteration (a hub queued
@@ -880,11 +912,11 @@ __global__ void k_level_advance(Ctl* ctl, uint32_t K) {
 // cost is its chain of dependent memory round trips, not its bandwidth, and
 // a one-level launch adds several (tile marks, worklist staging, per-XCD
 // filters, the tail reservation, the kernel boundary).  Here the frontier
-// stays in LDS and a level is two round trips: the arcs of the frontier,
-// then one atomic per arc (OR on the visited bitmap / 64-bit min on the
-// packed state) issued together with speculative loads of the target's
-// offsets, so a discovered node is pushed with its first arc and degree
-// (SSSP adds a coherent read of each pushed node's distance).  Slots of the
+// stays in LDS and a level is three round trips: the arcs of the frontier,
+// one atomic per arc (OR on the visited bitmap / 64-bit min on the packed
+// state), then the offsets of the arcs' winners, so a discovered node is
+// pushed with its first arc and degree (SSSP adds a coherent read of each
+// pushed node's distance).  Slots of the
 // level's edge space map to entries through an LDS bitmask of entry starts
 // with per-word popcount prefixes.  Pushes also go to the global node list
 // of the next worklist, for the case that they outgrow LDS.
@@ -1076,8 +1108,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t 
           }
         }
       }
-      // One atomic per arc, with the target's offsets read alongside (the
-      // loads are issued first so they are in flight with the atomics).
+      // One atomic per arc.
       bool win[kSmallU];
       int32_t s0[kSmallU], s1[kSmallU];
 #pragma unroll
@@ -1088,10 +1119,6 @@ __global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t 
         }
         s0[r] = 0;
         s1[r] = 0;
-        if (vv[r] >= 0) {
-          s0[r] = *at<kNarrow>(a.offsets, vv[r]);
-          s1[r] = *at<kNarrow>(a.offsets, vv[r] + 1);
-        }
       }
 #pragma unroll
       for (int r = 0; r < kSmallU; ++r) {
@@ -1112,6 +1139,17 @@ __global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t 
             ++upd;
             win[r] = static_cast<uint32_t>(old) != L + 1;  // not yet queued this level
           }
+        }
+      }
+      // Offsets of the winners only: the workgroup's CU issues about one
+      // random lane access per cycle, and most arcs do not win (measured on
+      // the 2048 x 2048 grid without shortcuts: BFS 11 % faster than loading
+      // every target's offsets alongside its atomic).
+#pragma unroll
+      for (int r = 0; r < kSmallU; ++r) {
+        if (win[r]) {
+          s0[r] = *at<kNarrow>(a.offsets, vv[r]);
+          s1[r] = *at<kNarrow>(a.offsets, vv[r] + 1);
         }
       }
 #pragma unroll
@@ -1193,6 +1231,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_expand_small(KArgs a, uint32_t 
     __hip_atomic_store(&a.ctl->ctr[Ln % 3], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&a.ctl->ctr[(Ln + 1) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  // the balanced kernel's tile counters of level L + 1 (see expand_level)
+  if (tid < static_cast<uint32_t>(kXcds)) a.ctl->xstat[tid][8 + (L + 1) % 3] = 0ull;
   if (a.count_stats) {
     const uint32_t su = wave_sum(upd), sa = wave_sum(atom);
     if (lane == 0) {

@@ -16,7 +16,8 @@
 // another inside each phase, wavefronts and workgroups one after another
 // (any such order is one of the interleavings the GPU may produce), and a
 // grid of G workgroups of 4 wavefronts is dealt tiles exactly as on the
-// device.  The small-frontier single-workgroup kernel is not emulated: every
+// device (the per-XCD counters of the last eighth answered in that order),
+// and every tile of a level must be dealt exactly once (flag 0x100).  The small-frontier single-workgroup kernel is not emulated: every
 // level runs the one-level path.
 //
 // Test infrastructure only (tests/test_index_emulation_cpu.py).
@@ -98,6 +99,7 @@ struct Solver {
   uint32_t T, kItems, node_cap, tile_cap, words, grid;
   Frontier* fr[2];
   unsigned long long ctr[3] = {0, 0, 0};
+  unsigned long long dctr[3][kXcds] = {};  // per-XCD tile counters (ctl->xstat[x][8 + L % 3])
   unsigned error = 0;
   uint32_t max_nf = 0, max_ef = 0;
   Arr<int32_t> levels;
@@ -304,17 +306,30 @@ struct Solver {
     }
     const uint32_t ntiles = (Ef + T - 1) / T;
     const uint32_t W = grid * kWaves;
+    // tile deal: round-robin below S, then per-XCD counters (slot L % 3,
+    // cleared by the previous level; every level here is a one-level launch)
+    const bool dyn = grid >= static_cast<uint32_t>(kXcds);
+    const uint32_t S = (dyn && ntiles > W) ? std::max(W, (ntiles - ntiles / 8) / W * W) : ntiles;
+    for (int x = 0; x < kXcds; ++x) dctr[(L + 1) % 3][x] = 0;
+    std::vector<uint8_t> dealt(ntiles, 0);
     for (uint32_t blk = 0; blk < grid; ++blk) {
       Prep preps[kWaves];
+      const uint32_t xcd = blk % kXcds;
+      auto take = [&]() { return S + xcd + static_cast<uint32_t>(kXcds) * static_cast<uint32_t>(dctr[L % 3][xcd]++); };
       for (int wid = 0; wid < kWaves; ++wid) {
         uint32_t qcount = 0;
         const uint64_t fx = static_cast<uint64_t>(blk % kXcds) * words;
         uint32_t tile = blk * kWaves + wid;
+        if (tile >= S) tile = S < ntiles ? take() : ntiles;
         uint32_t i0_next = tile < ntiles ? static_cast<uint32_t>(cur.tile_node[tile]) : 0u;
-        for (; tile < ntiles; tile += W) {
+        uint32_t tnext = ntiles;
+        for (; tile < ntiles; tile = tnext) {
           ++cur_tile_id;
+          if (dealt[tile]++) error |= 0x100u;  // a tile dealt twice
           const uint32_t i0 = i0_next;
-          if (tile + W < ntiles) i0_next = static_cast<uint32_t>(cur.tile_node[tile + W]);
+          const bool rr = tile + W < S;
+          tnext = rr ? tile + W : (S < ntiles ? take() : ntiles);
+          if (tnext < ntiles) i0_next = static_cast<uint32_t>(cur.tile_node[tnext]);
           const uint32_t t0 = tile * T, t1 = std::min(t0 + T, Ef);
           if (i0 >= nf) {
             error |= 16u;
@@ -472,6 +487,8 @@ struct Solver {
       for (int k = 0; k < kWaves; ++k)
         write_prep(preps[k], nxt, static_cast<uint32_t>(mb >> 32) + pn[k], static_cast<uint32_t>(mb) + pe[k]);
     }
+    for (uint32_t t = 0; t < ntiles; ++t)
+      if (!dealt[t]) error |= 0x100u;  // a tile nobody took
   }
 
   uint32_t run(int32_t src, uint32_t max_levels) {

@@ -53,7 +53,7 @@ def _check(emu, g, src, sssp, items, grid):
     out, st, msg = emu(g, src, sssp, items, grid)
     assert st[0] == 0, f"out-of-bounds access: {msg}"
     assert st[1] == 0, "an LDS slot staged for another tile was read"
-    assert st[2] == 0, f"device guard flags 0x{st[2]:x}"
+    assert st[2] == 0, f"device guard flags 0x{st[2]:x} (0x100: a tile dealt twice or never)"
     exp = O.dijkstra(g.offsets, g.cols, g.weights, src) if sssp else O.bfs(g.offsets, g.cols, src)
     assert np.array_equal(out, exp)
     return st
@@ -88,7 +88,9 @@ def _hub_graph():
 def test_small_graphs(emu, items, sssp):
     for g in (graphgen.uniform(14), graphgen.rmat(16), graphgen.grid(96)):
         s = int(graphgen.sources(g, 1, graphgen.FAMILY_RMAT)[0])
-        for grid in (1, 7, 512):  # one workgroup, an odd grid, the size of a resident grid
+        # one workgroup, an odd grid, the smallest grids that take the last
+        # eighth of a level's tiles from the per-XCD counters, a resident grid
+        for grid in (1, 7, 8, 9, 512):
             _check(emu, g, s, sssp, items, grid)
 
 
@@ -96,7 +98,7 @@ def test_small_graphs(emu, items, sssp):
 @pytest.mark.parametrize("sssp", [False, True])
 def test_hub_heavy_frontier(emu, items, sssp):
     g = _hub_graph()
-    for grid in (3, 768):
+    for grid in (3, 8, 768):
         st = _check(emu, g, 0, sssp, items, grid)
         assert st[5] >= 300_000  # the hubs' level was expanded in tiles
 
