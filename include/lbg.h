@@ -154,6 +154,19 @@ int lbg_bfs(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, i
             int32_t* levels_out, void* workspace, size_t workspace_bytes, int32_t strategy,
             const int32_t* coo_src, lbg_stats* stats, void* stream);
 
+/* Scan levels of balanced BFS (Section II-B's worklist, built by a scan).
+ * A level of lbg_bfs with LBG_BALANCED (or LBG_AUTO) whose frontier has at
+ * least `arcs` out-arcs is expanded without claim atomics or pushes: each
+ * newly reached node gets its level by a plain store, then one pass over the
+ * levels array builds the next worklist from the nodes of the new level, in
+ * node order.  Smaller levels claim and push as before.  Results are the
+ * same either way.  arcs < 0 (the default): n / 4 for a graph of n nodes;
+ * 0: every level; >= 2^32: never.  Process-wide, read when a solve starts;
+ * lbg_get_bfs_scan_min returns the setting (-1 for the default).  Always
+ * LBG_OK. */
+int lbg_set_bfs_scan_min(int64_t arcs);
+int64_t lbg_get_bfs_scan_min(void);
+
 /* SSSP distances from src.  dist_out[v] = minimum total weight of a directed
  * path from src to v, UINT32_MAX if unreachable.  Precondition: every finite
  * shortest-path weight is below UINT32_MAX (e.g. (n-1) * max weight <

@@ -60,7 +60,8 @@ struct Ctl {
   unsigned int level_base;    // graph-launched batches: first level of the next replay
   unsigned int sub_cnt[3];    // hierarchical strategy: sublist sizes of three sub-iterations
   unsigned int pad3;
-  unsigned long long pad1[4];
+  unsigned long long scan_levels;  // BFS: bit L set when level L (< 64) ran in scan mode
+  unsigned long long pad1[3];
   // [x][0] updates, [x][1] global atomics issued; [x][2], [x][3] the same for
   // levels run by the small-frontier kernel; [x][4 + L % 3] the packed tail
   // (nodes << 32 | edges) of slice x's worklist of level L (destination-
@@ -93,7 +94,7 @@ struct KArgs {
   const int32_t* coo_src;
   int32_t* levels;       // BFS output
   uint32_t* dist;        // SSSP output
-  uint32_t* visited;     // BFS: one bit per node (authoritative, set by atomicOr only)
+  uint32_t* visited;     // BFS: one bit per node (set by claim atomics, or by k_bfs_compact for scan levels)
   uint32_t* seen[2];     // BFS: read-only-per-level snapshots of `visited` (double-buffered)
   uint32_t* xfilter;     // BFS: per-XCD advisory copy of `visited`, kXcds x words
   unsigned long long* dstate;  // SSSP: (distance << 32) | iteration of last improvement
@@ -112,6 +113,10 @@ struct KArgs {
   uint32_t tile_cap;     // entries per tile_node array
   uint32_t edge_cap;     // entries per edge worklist
   uint32_t count_stats;
+  // BFS single solves on the balanced strategy: a level of at least scan_min
+  // arcs runs in scan mode (no claim atomics, no pushes; k_bfs_compact
+  // builds the next worklist from the levels array).  UINT32_MAX: never.
+  uint32_t scan_min;
   const QInfo* qtab;     // batched solves
   uint32_t num_queries;
   uint32_t rows;         // batched solves: total elements of node state

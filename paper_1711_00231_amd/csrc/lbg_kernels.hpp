@@ -297,6 +297,7 @@ __device__ __forceinline__ void init_state(const KArgs& a, int32_t src, uint32_t
     a.ctl->edges_scanned = 0ull;
     a.ctl->p_frontier_entries = 0ull;
     a.ctl->p_edges_scanned = 0ull;
+    a.ctl->scan_levels = 0ull;
   }
 }
 
@@ -516,6 +517,8 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
   const uint32_t state_len = kMulti ? a.rows : a.n;
   uint32_t upd = 0, atom = 0, qcount = 0, skip = 0;
   if (!kSssp) refresh_seen(a, L);
+  // BFS scan mode (see k_bfs_compact): grid-uniform
+  const bool scan = !kSssp && !kMulti && !kSplit && Ef >= a.scan_min;
 
   const uint32_t ntiles = (Ef + T - 1) / T;
   const uint32_t W = gridDim.x * kWaves;
@@ -725,16 +728,39 @@ __device__ __forceinline__ void expand_level(const KArgs& a, uint32_t L, unsigne
       uint32_t x[kItems];
 #pragma unroll
       for (int r = 0; r < kItems; ++r) x[r] = vv[r] >= 0 ? *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) : ~0u;
+      if (scan) {
+        // Scan mode: a candidate reads its node's level, which is exact
+        // for every earlier level (written by earlier launches), and an
+        // unvisited node gets level L + 1 by a plain store.  Several
+        // writers of one node store the same value; a stale read inside
+        // the level only repeats that store.  No claim, no push.
+        int32_t lv[kItems];
 #pragma unroll
-      for (int r = 0; r < kItems; ++r) {
-        const uint32_t bit = 1u << (vv[r] & 31);
-        const bool cand = vv[r] >= 0 && !(x[r] & bit);
-        if (cand) {
-          *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) = x[r] | bit;  // a lost bit costs one more atomic
-          ++atom;
-          x[r] = atomicOr(at<kNarrow>(a.visited, static_cast<uint32_t>(vv[r]) >> 5), bit);
-        } else {
-          x[r] = ~0u;
+        for (int r = 0; r < kItems; ++r) {
+          const uint32_t bit = 1u << (vv[r] & 31);
+          lv[r] = 0;
+          if (vv[r] >= 0 && !(x[r] & bit)) {
+            *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) = x[r] | bit;  // advisory
+            lv[r] = *at<kNarrow>(a.levels, vv[r]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+          if (lv[r] == static_cast<int32_t>(kBfsInf)) *at<kNarrow>(a.levels, vv[r]) = static_cast<int32_t>(L + 1);
+          x[r] = ~0u;  // nothing to push
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+          const uint32_t bit = 1u << (vv[r] & 31);
+          const bool cand = vv[r] >= 0 && !(x[r] & bit);
+          if (cand) {
+            *at<kNarrow>(fx, static_cast<uint32_t>(vv[r]) >> 5) = x[r] | bit;  // a lost bit costs one more atomic
+            ++atom;
+            x[r] = atomicOr(at<kNarrow>(a.visited, static_cast<uint32_t>(vv[r]) >> 5), bit);
+          } else {
+            x[r] = ~0u;
+          }
         }
       }
 #pragma unroll
@@ -891,6 +917,125 @@ __device__ __forceinline__ void balanced_level(const KArgs& a, uint32_t L) {
 template <bool kSssp, bool kNarrow, bool kMulti = false, bool kPacked = false, bool kSplit = false>
 __global__ __launch_bounds__(kBlock) void k_expand_balanced(KArgs a, uint32_t L) {
   balanced_level<kSssp, kNarrow, kMulti, kPacked, kSplit>(a, L);
+}
+
+// BFS scan levels.  A level of at least a.scan_min arcs is expanded without
+// claims or pushes (expand_level, scan mode): every newly reached node gets
+// level L + 1 in the levels array.  This kernel, launched after each
+// balanced BFS level, then builds worklist L + 1 from the nodes whose level
+// is L + 1 (the worklist of Section II-B, made by a scan of the node states
+// instead of by atomic claims; at R-MAT scale 22 a big level issues ~8 M
+// claim atomics, at a memory-side rate of ~25 G/s).  Each workgroup takes
+// 4096-node chunks: coalesced loads of the chunk's levels and offsets into
+// LDS, then thread t handles nodes 16t .. 16t + 15 of the chunk, so a block
+// scan gives every new node with out-arcs its place in node order and one
+// packed atomic reserves the chunk's entries: the next level reads the CSR
+// in order.  `visited` and next level's `seen` snapshot are rewritten from
+// the levels (each 32-node word by one thread, plain stores).
+// Returns at once after a push-mode level, whose pushes already built
+// worklist L + 1.  The host launches it only after levels it allows to scan
+// (it passes scan_min = UINT32_MAX to the expansion of any other level), so
+// a scan level is always followed by its compaction.
+constexpr uint32_t kCompactPer = 16;                      // nodes per thread
+constexpr uint32_t kCompactChunk = kBlock * kCompactPer;  // nodes per workgroup step
+__device__ __forceinline__ uint32_t compact_slot(uint32_t j) { return j + (j >> 4); }  // one pad word per 16
+
+template <bool kNarrow>
+__global__ __launch_bounds__(kBlock) void k_bfs_compact(KArgs a, uint32_t L) {
+  constexpr uint32_t T = TileCfg<false>::kEdges;
+  constexpr uint32_t kSlots = kCompactChunk + kCompactChunk / 16 + 1;
+  __shared__ int32_t lvs[kSlots];
+  __shared__ int32_t offs[kSlots];
+  __shared__ uint32_t wsum[2][kWaves];
+  __shared__ unsigned long long base_sh;
+  const unsigned long long c = __hip_atomic_load(&a.ctl->ctr[L % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t Ef = static_cast<uint32_t>(c);
+  if (Ef == 0u || Ef < a.scan_min || !level_fits<false, false>(a, c)) return;  // push-mode level
+  if (blockIdx.x == 0 && threadIdx.x == 0 && L < 64u) atomicOr(&a.ctl->scan_levels, 1ull << L);
+  Frontier nxt = a.fr[(L + 1) & 1];
+  nxt.level = L + 1;
+  const int nctr = (L + 1) % 3;
+  uint32_t* seen_nxt = a.seen[(L + 1) & 1];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int32_t want = static_cast<int32_t>(L + 1);
+  uint32_t upd = 0;
+  for (uint32_t c0 = blockIdx.x * kCompactChunk; c0 < a.n; c0 += gridDim.x * kCompactChunk) {
+    // the chunk's levels and offsets (offsets of nodes c0 .. c0 + 4096)
+#pragma unroll
+    for (uint32_t k = 0; k < kCompactPer; ++k) {
+      const uint32_t j = k * kBlock + tid, v = c0 + j;
+      lvs[compact_slot(j)] = v < a.n ? *at<kNarrow>(a.levels, v) : 0;
+      offs[compact_slot(j)] = v <= a.n ? *at<kNarrow>(a.offsets, v) : 0;
+    }
+    if (tid == 0) {
+      const uint32_t v = c0 + kCompactChunk;
+      offs[compact_slot(kCompactChunk)] = v <= a.n ? *at<kNarrow>(a.offsets, v) : 0;
+    }
+    __syncthreads();
+    // this thread's 16 nodes: which are new, their degrees
+    const uint32_t j0 = tid * kCompactPer;
+    uint32_t newm = 0, reached = 0, cnt = 0, deg = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kCompactPer; ++k) {
+      const uint32_t j = j0 + k;
+      const int32_t lv = lvs[compact_slot(j)];
+      if (c0 + j < a.n && lv != static_cast<int32_t>(kBfsInf)) reached |= 1u << k;
+      if (c0 + j < a.n && lv == want) {
+        newm |= 1u << k;
+        const uint32_t d = static_cast<uint32_t>(offs[compact_slot(j + 1)] - offs[compact_slot(j)]);
+        cnt += d > 0u ? 1u : 0u;
+        deg += d;
+      }
+    }
+    upd += __popc(newm);
+    // The chunk's 32-node words of `visited` and of next level's `seen`:
+    // every node of level <= L + 1, which is exactly what the levels say
+    // now, so the even thread of a pair stores whole words, no read needed.
+    const uint32_t pair = static_cast<uint32_t>(__shfl_xor(static_cast<int>(reached), 1, 64));
+    if (!(tid & 1u) && c0 + j0 < a.n) {
+      const uint32_t word = reached | (pair << 16);
+      const uint32_t w = (c0 + j0) >> 5;
+      *at<kNarrow>(a.visited, w) = word;
+      *at<kNarrow>(seen_nxt, w) = word;
+    }
+    // block exclusive scan of (entries, arcs) in node order, one reservation
+    const uint32_t ic = wave_incl_scan(cnt), ie = wave_incl_scan(deg);
+    if (lane == 63) {
+      wsum[0][wid] = ic;
+      wsum[1][wid] = ie;
+    }
+    __syncthreads();
+    uint32_t pc = ic - cnt, pe = ie - deg, tc = 0, te = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      if (static_cast<uint32_t>(k) < wid) {
+        pc += wsum[0][k];
+        pe += wsum[1][k];
+      }
+      tc += wsum[0][k];
+      te += wsum[1][k];
+    }
+    if (tid == 0) base_sh = tc ? atomicAdd(&a.ctl->ctr[nctr], (static_cast<unsigned long long>(tc) << 32) | te) : 0ull;
+    __syncthreads();
+    const uint32_t nb = static_cast<uint32_t>(base_sh >> 32) + pc;
+    uint32_t eb = static_cast<uint32_t>(base_sh) + pe;
+    uint32_t i = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kCompactPer; ++k) {
+      const uint32_t j = j0 + k;
+      if (newm & (1u << k)) {
+        const int32_t s = offs[compact_slot(j)];
+        const int32_t d = offs[compact_slot(j + 1)] - s;
+        if (d > 0) {
+          write_entry<0, T, kNarrow>(a, nxt, nb + i, eb, static_cast<int32_t>(c0 + j), 0, s, d);
+          ++i;
+          eb += static_cast<uint32_t>(d);
+        }
+      }
+    }
+    __syncthreads();  // LDS reused by the next chunk
+  }
+  add_stats(a, upd, 0u);
 }
 
 // Graph-launched batches: one replay of a graph runs levels level_base + k

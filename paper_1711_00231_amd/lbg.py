@@ -98,6 +98,10 @@ def _load():
     lib.lbg_slice_nodes.argtypes = [i32]
     lib.lbg_set_slice_min.restype = ctypes.c_int
     lib.lbg_set_slice_min.argtypes = [i32]
+    lib.lbg_set_bfs_scan_min.restype = ctypes.c_int
+    lib.lbg_set_bfs_scan_min.argtypes = [i64]
+    lib.lbg_get_bfs_scan_min.restype = i64
+    lib.lbg_get_bfs_scan_min.argtypes = []
     lib.lbg_get_slice_min.restype = i32
     lib.lbg_get_slice_min.argtypes = []
     lib.lbg_slice_graph.restype = ctypes.c_int
@@ -319,6 +323,16 @@ def set_slice_min(min_degree: int) -> None:
 
 def get_slice_min() -> int:
     return int(lib.lbg_get_slice_min())
+
+
+def set_bfs_scan_min(arcs: int) -> None:
+    """Frontier arcs from which a balanced BFS level runs in scan mode
+    (< 0: n / 4, 0: every level, >= 2**32: never; see lbg_set_bfs_scan_min)."""
+    _check(lib.lbg_set_bfs_scan_min(int(arcs)))
+
+
+def get_bfs_scan_min() -> int:
+    return int(lib.lbg_get_bfs_scan_min())
 
 
 def slice_graph(g: DeviceGraph, stream=None) -> SlicedGraph:

@@ -102,6 +102,8 @@ struct Solver {
   unsigned long long dctr[3][kXcds] = {};  // per-XCD tile counters (ctl->xstat[x][8 + L % 3])
   unsigned error = 0;
   uint32_t max_nf = 0, max_ef = 0;
+  uint32_t scan_min = 0xffffffffu;  // BFS: levels of at least this many arcs run in scan mode
+  long scan_levels = 0;
   Arr<int32_t> levels;
   Arr<uint32_t> visited, seen0, seen1, xfilter;
   Arr<unsigned long long> dstate;
@@ -296,6 +298,7 @@ struct Solver {
     Frontier& cur = *fr[L & 1];
     Frontier& nxt = *fr[(L + 1) & 1];
     const int nctr = (L + 1) % 3;
+    const bool scan = !kSssp && Ef >= scan_min;
     if (!kSssp) {  // refresh_seen by the whole grid
       for (uint32_t k = 0; k < words; ++k) seen((L + 1) & 1)[k] = seen(L & 1)[k];
       for (uint32_t x = 0; x < kXcds; ++x)
@@ -419,7 +422,17 @@ struct Solver {
               x = -1;
             }
           std::vector<char> push(kItems * 64, 0);
-          if (!kSssp) {
+          if (!kSssp && scan) {
+            // scan mode: an unvisited node gets level L + 1, nothing is pushed
+            for (uint32_t q = 0; q < kItems * 64; ++q) {
+              if (vv[q] < 0) continue;
+              const uint32_t v = static_cast<uint32_t>(vv[q]), bit = 1u << (v & 31);
+              const uint32_t x = xfilter[fx + (v >> 5)];
+              if (x & bit) continue;
+              xfilter[fx + (v >> 5)] = x | bit;
+              if (levels[v] == static_cast<int32_t>(kBfsInf)) levels[v] = static_cast<int32_t>(L + 1);
+            }
+          } else if (!kSssp) {
             for (uint32_t q = 0; q < kItems * 64; ++q) {
               if (vv[q] < 0) continue;
               const uint32_t v = static_cast<uint32_t>(vv[q]), bit = 1u << (v & 31);
@@ -489,6 +502,80 @@ struct Solver {
     }
     for (uint32_t t = 0; t < ntiles; ++t)
       if (!dealt[t]) error |= 0x100u;  // a tile nobody took
+    if (scan) compact(L);
+  }
+
+  // k_bfs_compact after a scan-mode level: worklist L + 1 from the nodes of
+  // level L + 1, 4096-node chunks per workgroup (grid: one per chunk, at most
+  // the expansion's grid), 16 consecutive nodes per thread, LDS slots padded
+  // one word per 16, one reservation per chunk, entries in node order.
+  void compact(uint32_t L) {
+    ++scan_levels;
+    constexpr uint32_t kBlock = 256, kPer = 16, kChunk = kBlock * kPer;
+    constexpr uint32_t kSlots = kChunk + kChunk / 16 + 1;
+    auto slot = [](uint32_t j) { return j + (j >> 4); };
+    Arr<int32_t> lvs("lds.compact.levels", kSlots), offs("lds.compact.offsets", kSlots);
+    Frontier& nxt = *fr[(L + 1) & 1];
+    const int nctr = (L + 1) % 3;
+    const int32_t want = static_cast<int32_t>(L + 1);
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>((g.n + kChunk - 1) / kChunk, grid));
+    for (uint32_t b = 0; b < blocks; ++b) {
+      for (uint32_t c0 = b * kChunk; c0 < g.n; c0 += blocks * kChunk) {
+        for (uint32_t k = 0; k < kPer; ++k)
+          for (uint32_t tid = 0; tid < kBlock; ++tid) {
+            const uint32_t j = k * kBlock + tid, v = c0 + j;
+            lvs[slot(j)] = v < g.n ? levels[v] : 0;
+            offs[slot(j)] = v <= g.n ? (*g.offsets)[v] : 0;
+          }
+        {
+          const uint32_t v = c0 + kChunk;
+          offs[slot(kChunk)] = v <= g.n ? (*g.offsets)[v] : 0;
+        }
+        uint32_t newm[kBlock], reached[kBlock], cnt[kBlock], deg[kBlock];
+        for (uint32_t tid = 0; tid < kBlock; ++tid) {
+          newm[tid] = reached[tid] = cnt[tid] = deg[tid] = 0;
+          for (uint32_t k = 0; k < kPer; ++k) {
+            const uint32_t j = tid * kPer + k;
+            if (c0 + j < g.n && lvs[slot(j)] != static_cast<int32_t>(kBfsInf)) reached[tid] |= 1u << k;
+            if (c0 + j < g.n && lvs[slot(j)] == want) {
+              newm[tid] |= 1u << k;
+              const uint32_t d = static_cast<uint32_t>(offs[slot(j + 1)] - offs[slot(j)]);
+              cnt[tid] += d > 0u ? 1u : 0u;
+              deg[tid] += d;
+            }
+          }
+        }
+        for (uint32_t tid = 0; tid < kBlock; tid += 2) {
+          if (c0 + tid * kPer >= g.n) continue;
+          const uint32_t word = reached[tid] | (reached[tid + 1] << 16);
+          const uint32_t w = (c0 + tid * kPer) >> 5;
+          // the words must equal what the claims of push levels left
+          // (every reached node, no other bit): checked before storing
+          if ((visited[w] | (newm[tid] | (newm[tid + 1] << 16))) != word) error |= 0x200u;
+          visited[w] = word;
+          seen((L + 1) & 1)[w] = word;
+        }
+        uint32_t tc = 0, te = 0;
+        for (uint32_t tid = 0; tid < kBlock; ++tid) {
+          tc += cnt[tid];
+          te += deg[tid];
+        }
+        const unsigned long long mb = ctr[nctr];
+        if (tc) ctr[nctr] += (static_cast<unsigned long long>(tc) << 32) | te;
+        uint32_t nb = static_cast<uint32_t>(mb >> 32), eb = static_cast<uint32_t>(mb);
+        for (uint32_t tid = 0; tid < kBlock; ++tid)
+          for (uint32_t k = 0; k < kPer; ++k) {
+            const uint32_t j = tid * kPer + k;
+            if (!(newm[tid] & (1u << k))) continue;
+            const int32_t s = offs[slot(j)];
+            const int32_t d = offs[slot(j + 1)] - s;
+            if (d > 0) {
+              write_entry(nxt, nb++, eb, static_cast<int32_t>(c0 + j), s, d);
+              eb += static_cast<uint32_t>(d);
+            }
+          }
+      }
+    }
   }
 
   uint32_t run(int32_t src, uint32_t max_levels) {
@@ -510,13 +597,14 @@ extern "C" {
 // BFS (is_sssp = 0) or SSSP (1) from src with tiles of 64 x items arcs,
 // tile marks sized by min_tile (the smallest tile any single-solve kernel
 // uses), a grid of grid_blocks workgroups.  out: int32 levels or uint32
-// distances, n entries.  stats[0..5]: out-of-bounds accesses, stale LDS
+// distances, n entries.  BFS levels of at least scan_min arcs run in scan
+// mode (UINT32_MAX: never).  stats[0..6]: out-of-bounds accesses, stale LDS
 // reads, device guard flags raised, levels run, entries and edges of the
-// largest level.
+// largest level, levels run in scan mode.
 // msg: the first out-of-bounds access (empty when none).
 int emu_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weights, uint32_t n, uint32_t m,
-              int32_t src, int is_sssp, uint32_t items, uint32_t min_tile, uint32_t grid_blocks, void* out,
-              long* stats, char* msg, int msg_len) {
+              int32_t src, int is_sssp, uint32_t items, uint32_t min_tile, uint32_t grid_blocks,
+              uint32_t scan_min, void* out, long* stats, char* msg, int msg_len) {
   Report rep;
   R = &rep;
   Arr<int32_t> off("offsets", n + 1), cl("cols", m);
@@ -526,6 +614,7 @@ int emu_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weigh
   if (is_sssp && m) memcpy(wt.v.data(), weights, sizeof(uint32_t) * m);
   Graph g{&off, &cl, &wt, n, m};
   uint32_t levels = 0, mnf = 0, mef = 0;
+  long scans = 0;
   unsigned err = 0;
   if (is_sssp) {
     Solver<true> s(g, items, min_tile, grid_blocks);
@@ -537,10 +626,12 @@ int emu_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weigh
     for (uint32_t v = 0; v < n; ++v) d[v] = static_cast<uint32_t>(s.dstate.v[v] >> 32);
   } else {
     Solver<false> s(g, items, min_tile, grid_blocks);
+    s.scan_min = scan_min;
     levels = s.run(src, n + 2);
     err = s.error;
     mnf = s.max_nf;
     mef = s.max_ef;
+    scans = s.scan_levels;
     memcpy(out, s.levels.v.data(), sizeof(int32_t) * n);
   }
   stats[0] = rep.violations;
@@ -549,6 +640,7 @@ int emu_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* weigh
   stats[3] = static_cast<long>(levels);
   stats[4] = static_cast<long>(mnf);
   stats[5] = static_cast<long>(mef);
+  stats[6] = scans;
   snprintf(msg, static_cast<size_t>(msg_len), "%s", rep.first);
   R = nullptr;
   return 0;

@@ -20,6 +20,7 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 O = oracle.get()
 MIN_TILE = 512  # the single-solve tile marks are sized by the SSSP tile (64 x 8 arcs)
+NEVER = 0xFFFFFFFF  # BFS scan mode off
 
 
 @pytest.fixture(scope="module")
@@ -32,25 +33,25 @@ def emu(tmp_path_factory):
     lib = ctypes.CDLL(so)
     vp = ctypes.c_void_p
     u32 = ctypes.c_uint32
-    lib.emu_solve.argtypes = [vp, vp, vp, u32, u32, ctypes.c_int32, ctypes.c_int, u32, u32, u32, vp, vp,
+    lib.emu_solve.argtypes = [vp, vp, vp, u32, u32, ctypes.c_int32, ctypes.c_int, u32, u32, u32, u32, vp, vp,
                               ctypes.c_char_p, ctypes.c_int]
 
-    def run(g, src, sssp, items, grid):
+    def run(g, src, sssp, items, grid, scan_min=NEVER):
         out = np.empty(g.n, dtype=np.uint32 if sssp else np.int32)
-        st = np.zeros(6, dtype=np.int64)
+        st = np.zeros(7, dtype=np.int64)
         msg = ctypes.create_string_buffer(512)
         off = np.ascontiguousarray(g.offsets, dtype=np.int32)
         cols = np.ascontiguousarray(g.cols, dtype=np.int32)
         w = np.ascontiguousarray(g.weights if g.weights is not None else np.ones(g.m), dtype=np.uint32)
         lib.emu_solve(off.ctypes.data, cols.ctypes.data, w.ctypes.data, g.n, g.m, int(src), int(sssp), items,
-                      MIN_TILE, grid, out.ctypes.data, st.ctypes.data, msg, 512)
+                      MIN_TILE, grid, scan_min, out.ctypes.data, st.ctypes.data, msg, 512)
         return out, st, msg.value.decode()
 
     return run
 
 
-def _check(emu, g, src, sssp, items, grid):
-    out, st, msg = emu(g, src, sssp, items, grid)
+def _check(emu, g, src, sssp, items, grid, scan_min=NEVER):
+    out, st, msg = emu(g, src, sssp, items, grid, scan_min)
     assert st[0] == 0, f"out-of-bounds access: {msg}"
     assert st[1] == 0, "an LDS slot staged for another tile was read"
     assert st[2] == 0, f"device guard flags 0x{st[2]:x} (0x100: a tile dealt twice or never)"
@@ -124,3 +125,34 @@ def test_rmat22_levels(emu, rmat22, sssp, items):
     g, srcs = rmat22
     st = _check(emu, g, int(srcs[0]), sssp, items, 768)
     assert st[5] > 100_000_000
+
+
+@pytest.mark.parametrize("rule", ["every", "quarter_n"])
+def test_bfs_scan_levels(emu, rule):
+    """BFS levels expanded in scan mode (plain level stores, no claims or
+    pushes) and the compaction that builds the next worklist in node order:
+    every level (threshold 0) or the library's default, levels of at least
+    n / 4 arcs, mixed with push-mode levels; on the three families, the hub
+    frontier and one-node / star graphs, grids from one workgroup to a
+    resident one (the compaction's grid is one workgroup per 4096 nodes, at
+    most the expansion's)."""
+    graphs = [graphgen.uniform(14), graphgen.rmat(16), graphgen.grid(96), _hub_graph(),
+              graphgen.from_edges(1, np.zeros(0), np.zeros(0), None, "single"),
+              graphgen.from_edges(1025, np.zeros(1024), np.arange(1, 1025), None, "star-1024")]
+    for g in graphs:
+        s = 0 if g.n <= 1025 or g.name == "hubs" else int(graphgen.sources(g, 1, graphgen.FAMILY_RMAT)[0])
+        scan_min = 0 if rule == "every" else max(1, g.n // 4)
+        for grid in (1, 9, 768):
+            st = _check(emu, g, s, False, 16, grid, scan_min)
+            if rule == "every" and g.m:
+                assert st[6] == st[3]  # every level ran in scan mode
+            if rule == "quarter_n" and g.name == "hubs":
+                assert 0 < st[6] < st[3]  # the hubs' level scanned, the others pushed
+
+
+def test_rmat22_scan_levels(emu, rmat22):
+    """R-MAT scale 22 with the default threshold (levels of >= n / 4 arcs
+    scan)."""
+    g, srcs = rmat22
+    st = _check(emu, g, int(srcs[0]), False, 16, 768, g.n // 4)
+    assert st[6] >= 2
