@@ -514,7 +514,7 @@ def run_batch(lbg, torch, dev, count, sources_per_instance, hi_exp, reps=3):
 
 # -------------------------------------------------------------- serving --
 def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_count=8,
-              big_arcs=1 << 23, workers=3, engine_only_fraction=None):
+              big_arcs=1 << 23, workers=3, engine_only_fraction=None, engine_yield_ms=0.0):
     """Serving over resident R-MAT instances plus per-request uploads.
     Instances of at least big_arcs arcs are served by a plain lane of
     `workers` solves that run at once (queries overlap on the device), the
@@ -627,7 +627,7 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
         reqs = requests_at(frac)
         arena = serve.UploadArena(dg, u.n, u.m, R, NC, MC)
         rep = serve.Server(eng, inst, upload=arena, plain=lane, idle_bypass=True,
-                           levels_per_step=2).run(reqs)
+                           levels_per_step=2, engine_yield=engine_yield_ms * 1e-3).run(reqs)
         s = rep.summary()
         done = sorted(rep.completed, key=lambda r: r.rid)
         s["by_target_p50_p99_ms"] = by_class(done, [r.latency * 1e3 for r in done])
@@ -641,6 +641,7 @@ def run_serve(lbg, torch, dev, scales, fractions, requests_per_point, upload_cou
            "plain_service_ms_p50": round(float(np.percentile(svc, 50)) * 1e3, 4),
            "plain_service_ms_p99": round(float(np.percentile(svc, 99)) * 1e3, 4),
            "lane_workers": workers,
+           "engine_yield_ms": engine_yield_ms,
            "points": points,
            "workload": f"resident R-MAT scales {list(scales)} (ef 16, symmetrised, weights "
                        f"U[1,255]) + per-request uploaded uniform graphs n in [2^12, 2^16]; "
@@ -788,6 +789,9 @@ def main():
                     help="do not bracket expansion launches with events (no roofline)")
     ap.add_argument("--no-extras", action="store_true",
                     help="plain mode: skip the compact batched and serving measurements")
+    ap.add_argument("--engine-yield-ms", type=float, default=0.0,
+                    help="serving: the engine waits while the plain lane has work, up to this "
+                         "long after admitting a query (0: never waits)")
     ap.add_argument("--lane-workers", type=int, default=3,
                     help="serving: plain solves of large resident instances that may run at once")
     ap.add_argument("--switch-interval-us", type=float, default=0.0,
@@ -833,7 +837,7 @@ def main():
     if args.mode == "serve":
         res = run_serve(lbg, torch, dev, scales=(20, 22, 24),
                         fractions=(0.25, 0.5, 0.75, 1.0, 1.25), requests_per_point=2000,
-                        workers=args.lane_workers)
+                        workers=args.lane_workers, engine_yield_ms=args.engine_yield_ms)
         p99 = max(p["p99_ms"] for p in res["points"])
         print(json.dumps({"metric": "served p99 latency (ms) over a QPS sweep", "value": p99,
                           "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "u32",

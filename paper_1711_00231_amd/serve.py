@@ -202,10 +202,33 @@ class PlainLane:
                         wait = self.overlap_after - waited
                 self._cv.wait(wait)
 
-    def start(self, clock, t0: float, keep_results: bool) -> None:
+    def prepare(self) -> None:
+        """Start the worker threads and let each run its solver's `warm`
+        hook (if it has one: a small solve that sets up the thread's GPU
+        state) before it takes any query; returns once all are warm.  A
+        server calls this before its clock starts, so the first queries do
+        not pay for that set-up."""
+        if self._threads:
+            return
         self._stopping = False
+        self._go = threading.Event()
+        self._run = {}
+        warm_left = [len(self.solvers)]
+        warm_cv = threading.Condition()
 
         def work(k, solve):
+            warm = getattr(solve, "warm", None)
+            try:
+                if warm is not None:
+                    warm()
+            except Exception as exc:  # surfaced by the serving loop
+                with self._lock:
+                    self._error = exc
+            with warm_cv:
+                warm_left[0] -= 1
+                warm_cv.notify_all()
+            self._go.wait()
+            clock, t0, keep_results = self._run["clock"], self._run["t0"], self._run["keep"]
             while True:
                 r = self._take(k, clock, t0)
                 if r is None:
@@ -234,6 +257,15 @@ class PlainLane:
                          for k, f in enumerate(self.solvers)]
         for t in self._threads:
             t.start()
+        with warm_cv:
+            while warm_left[0]:
+                warm_cv.wait()
+
+    def start(self, clock, t0: float, keep_results: bool) -> None:
+        """Let the workers take queries (times relative to t0)."""
+        self.prepare()
+        self._run = {"clock": clock, "t0": t0, "keep": keep_results}
+        self._go.set()
 
     def submit(self, r: Request) -> None:
         with self._lock:
@@ -257,6 +289,9 @@ class PlainLane:
         with self._cv:
             self._stopping = True
             self._cv.notify_all()
+        if self._threads and not self._go.is_set():  # prepared, never started
+            self._run = {"clock": time.perf_counter, "t0": 0.0, "keep": False}
+            self._go.set()
         for t in self._threads:
             t.join()
         self._threads = []
@@ -279,8 +314,13 @@ class Server:
 
     def __init__(self, engine, instances: dict, upload=None, levels_per_step: int = 1,
                  keep_results: bool = False, plain: PlainLane | None = None,
-                 timeout: float | None = None, idle_bypass: bool = False):
+                 timeout: float | None = None, idle_bypass: bool = False,
+                 engine_yield: float = 0.0):
         self.engine = engine
+        # > 0: while the plain lane has work, the engine takes no step until
+        # one of its queries has been admitted that many seconds ago, so a
+        # large plain solve runs without the engine's levels beside it
+        self.engine_yield = float(engine_yield)
         self.instances = instances
         self.upload = upload
         self.levels_per_step = int(levels_per_step)
@@ -390,8 +430,13 @@ class Server:
         pending = list(requests)
         by_rid = {r.rid: r for r in pending}
         report = ServeReport()
-        t0 = clock()
         lane = self.plain
+        if lane is not None:
+            lane.prepare()  # warm workers before the clock starts
+        warm = getattr(self.upload, "warm", None)  # optional for arena stand-ins
+        if warm is not None and not self.inflight:
+            warm()
+        t0 = clock()
         if lane is not None:
             lane.start(clock, t0, self.keep_results)
         i = 0
@@ -431,6 +476,10 @@ class Server:
                                            "(the engine or the upload arena has no capacity)")
                     wait = pending[i].arrival - (clock() - t0)
                     time.sleep(min(max(wait, 0.0), 0.001) if wait > 0 else 0.0001)
+                    continue
+                if (self.engine_yield > 0 and lane is not None and lane.busy()
+                        and all(now - r.admitted < self.engine_yield for r in self.inflight.values())):
+                    time.sleep(0.0001)
                     continue
                 done = self.engine.step(self.levels_per_step)
                 report.steps += 1
@@ -508,6 +557,23 @@ class UploadArena:
     def acquire(self):
         return self.free.pop(0) if self.free else None
 
+    def warm(self) -> None:
+        """Load a 2-node, 1-arc graph into a free region and free it again,
+        so the first real upload does not pay for the first launches of the
+        copy path's device operations (~17 ms measured).  Only while no
+        query uses the arena (a server calls it before its clock starts)."""
+        if not self.free:
+            return
+        from types import SimpleNamespace
+
+        tiny = SimpleNamespace(n=2, m=1, offsets=np.array([0, 1, 1], dtype=np.int32),
+                               cols=np.array([1], dtype=np.int32), weights=np.array([1], dtype=np.uint32))
+        region = self.acquire()
+        try:
+            self.load(region, tiny)
+        finally:
+            self.release(region)
+
     def release(self, region: int) -> None:
         self.free.append(region)
         self.free.sort()
@@ -519,14 +585,21 @@ class UploadArena:
             raise ValueError(f"graph with n={g.n}, m={g.m} exceeds the upload region")
         lo = self.node_base + region * self.node_cap
         a0 = self.arc_base + region * self.arc_cap
-        off = np.full(self.node_cap, a0 + g.m, dtype=np.int64)
-        off[: g.n + 1] = a0 + g.offsets.astype(np.int64)
-        dev = self.dg.offsets.device
-        self.dg.offsets[lo: lo + self.node_cap].copy_(torch.from_numpy(off.astype(np.int32)).to(dev))
+        # The graph's own arrays go into the region's slices as they are, and
+        # the region's node and arc bases are added on the device: no large
+        # host temporary is made inside the serving loop (measured: building
+        # the rebased columns on the host stalled the loop for 83 ms on the
+        # first upload of a run, in first-touch page faults of the new
+        # array), and no device temporary either.
+        offs = self.dg.offsets[lo: lo + self.node_cap]
+        offs[: g.n + 1].copy_(torch.from_numpy(np.ascontiguousarray(g.offsets, dtype=np.int32)))
+        offs[: g.n + 1] += a0
+        offs[g.n + 1:].fill_(a0 + g.m)  # the unused nodes and the sink own no arcs of the graph
         if g.m:
-            self.dg.cols[a0: a0 + g.m].copy_(
-                torch.from_numpy((g.cols.astype(np.int64) + lo).astype(np.int32)).to(dev))
-            self.dg.weights[a0: a0 + g.m].copy_(torch.from_numpy(g.weights.view(np.int32)).to(dev))
+            cols = self.dg.cols[a0: a0 + g.m]
+            cols.copy_(torch.from_numpy(np.ascontiguousarray(g.cols, dtype=np.int32)))
+            cols += lo
+            self.dg.weights[a0: a0 + g.m].copy_(torch.from_numpy(np.ascontiguousarray(g.weights).view(np.int32)))
         return lo, lo + g.n, g.m
 
 
@@ -569,6 +642,15 @@ def gpu_plain_lane(graphs: dict, big_arcs: int, ordered_sssp: bool = False, work
             with torch.cuda.stream(stream):
                 return out[: g.n].cpu().numpy()
 
+        def warm():
+            # one BFS and one SSSP on the smallest graph, from this thread:
+            # the library's per-thread state (pinned read-back word, events)
+            # is set up here rather than by a query
+            g = min(gs, key=lambda x: x.m)
+            lbg.bfs(g, 0, out=out[: g.n], workspace=ws, stream=stream)
+            lbg.sssp(g, 0, out=out[: g.n], workspace=ws, stream=stream, ordered=ordered_sssp)
+
+        solve.warm = warm
         return solve
 
     return PlainLane([make_solver() for _ in range(max(1, int(workers)))], big_arcs, names=graphs.keys(),

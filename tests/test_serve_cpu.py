@@ -238,6 +238,9 @@ def test_upload_region_layout_matches_graph():
         weights = torch.from_numpy(p_w.view(np.int32))
 
     arena = UploadArena(DG, base.n, base.m, R, NC, MC)
+    arena.warm()  # loads a tiny graph into a free region and frees it again
+    assert arena.free == list(range(R))
+    O.bfs(DG.offsets.numpy().astype(np.int64), DG.cols.numpy(), 0)  # packed CSR still valid
     for salt, region in ((1, arena.acquire()), (2, arena.acquire()), (3, 0)):
         g = graphgen.uniform(n=450 + 40 * salt, k=7, wlo=1, whi=30, salt=salt)
         lo, hi, arcs = arena.load(region, g)
@@ -339,6 +342,85 @@ def test_plain_lane_extra_workers_wait_for_a_backlog():
         r.arrival = 0.05 * i
     rep = serve.Server(eng, inst, plain=lane).run(reqs)
     assert len(rep.completed) == 8 and peak[0] == 1
+
+
+def test_engine_yields_to_a_busy_plain_lane():
+    """engine_yield: while a (slow) plain solve runs, the engine takes no
+    step until its query was admitted that long ago; without it the engine
+    steps at once.  Results are exact either way."""
+    import threading
+
+    gs, u, inst = _setup()
+    plain_running = threading.Event()
+
+    def slow(r, keep):
+        plain_running.set()
+        time.sleep(0.06)
+        plain_running.clear()
+        return None
+
+    def first_step_delay(yield_s):
+        eng = FakeEngine(u, max_queries=4, max_rows=6000, lag=1)
+        seen = {}
+        step0 = eng.step
+
+        def step(levels=1):
+            if plain_running.is_set() and "t" not in seen:
+                seen["t"] = time.perf_counter()
+            return step0(levels)
+        eng.step = step
+        lane = serve.PlainLane(slow, big_arcs=inst["g1"].arcs)  # R-MAT 11, the largest: plain lane
+        reqs = serve.poisson_requests(1e4, 2, inst, seed=5)
+        reqs[0].instance, reqs[0].src, reqs[0].arrival = "g1", 0, 0.0
+        reqs[1].instance, reqs[1].src, reqs[1].arrival = "g2", 0, 0.01  # the grid: engine
+        t0 = time.perf_counter()
+        rep = serve.Server(eng, inst, plain=lane, keep_results=True, engine_yield=yield_s).run(reqs)
+        assert len(rep.completed) == 2
+        _check_results(type(rep)(completed=[r for r in rep.completed if r.instance == "g2"]), gs)
+        return seen.get("t", float("inf")) - t0
+
+    assert first_step_delay(0.0) < 0.03        # steps beside the plain solve
+    assert first_step_delay(0.03) >= 0.035     # waits until its query is 30 ms old
+
+
+def test_plain_lane_warms_each_worker_before_the_clock():
+    """A solver's warm hook runs once, on its own worker thread, before the
+    server's clock starts and before the worker takes any query."""
+    import threading
+
+    gs, u, inst = _setup()
+    log = []
+    lock = threading.Lock()
+
+    def make(k):
+        def solve(r, keep):
+            with lock:
+                log.append(("solve", k, threading.get_ident(), time.perf_counter()))
+            return None
+
+        def warm():
+            with lock:
+                log.append(("warm", k, threading.get_ident(), time.perf_counter()))
+            time.sleep(0.02)
+        solve.warm = warm
+        return solve
+
+    lane = serve.PlainLane([make(k) for k in range(3)], big_arcs=0)
+    eng = FakeEngine(u, max_queries=2, max_rows=6000)
+    reqs = serve.poisson_requests(1e4, 12, inst, seed=23)
+    t_before = time.perf_counter()
+    serve.Server(eng, inst, plain=lane).run(reqs)
+    warms = [e for e in log if e[0] == "warm"]
+    solves = [e for e in log if e[0] == "solve"]
+    assert sorted(e[1] for e in warms) == [0, 1, 2]
+    assert len(solves) == 12
+    assert min(e[3] for e in solves) > max(e[3] for e in warms) >= t_before
+    thread_of = {e[1]: e[2] for e in warms}
+    assert all(thread_of[e[1]] == e[2] for e in solves)  # same thread as its warm-up
+    # a lane prepared and stopped without a run shuts down cleanly
+    lane2 = serve.PlainLane([make(k) for k in range(2)], big_arcs=0)
+    lane2.prepare()
+    lane2.stop()
 
 
 def test_plain_lane_error_surfaces():
