@@ -583,7 +583,9 @@ int solve(const Problem& P) {
           else hipLaunchKernelGGL((lbg::k_expand_balanced<false, false, false, false, true>), dim3(GR.bal_s[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
           break;
         default:
-          if (scan_at(L)) {  // may scan: the compaction follows
+          if (scan_at(L)) {  // may scan: the filter merge precedes, the compaction follows
+            if (narrow) hipLaunchKernelGGL((lbg::k_bfs_prep<true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
+            else hipLaunchKernelGGL((lbg::k_bfs_prep<false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
             if (narrow) hipLaunchKernelGGL((lbg::k_expand_balanced<false, true>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
             else hipLaunchKernelGGL((lbg::k_expand_balanced<false, false>), dim3(GR.bal[sv][nw]), dim3(lbg::kBlock), 0, st, a, L);
             if (narrow) hipLaunchKernelGGL((lbg::k_bfs_compact<true>), dim3(compact_blocks), dim3(lbg::kBlock), 0, st, a, L);

@@ -299,7 +299,11 @@ struct Solver {
     Frontier& nxt = *fr[(L + 1) & 1];
     const int nctr = (L + 1) % 3;
     const bool scan = !kSssp && Ef >= scan_min;
-    if (!kSssp) {  // refresh_seen by the whole grid
+    if (scan) {  // k_bfs_prep: every XCD's filter absorbs `visited`
+      for (uint32_t x = 0; x < kXcds; ++x)
+        for (uint32_t k = 0; k < words; ++k) xfilter[static_cast<uint64_t>(x) * words + k] |= visited[k];
+    }
+    if (!kSssp && !scan) {  // refresh_seen by the whole grid
       for (uint32_t k = 0; k < words; ++k) seen((L + 1) & 1)[k] = seen(L & 1)[k];
       for (uint32_t x = 0; x < kXcds; ++x)
         for (uint32_t k = 0; k < words; ++k) {
@@ -430,7 +434,10 @@ struct Solver {
               const uint32_t x = xfilter[fx + (v >> 5)];
               if (x & bit) continue;
               xfilter[fx + (v >> 5)] = x | bit;
-              if (levels[v] == static_cast<int32_t>(kBfsInf)) levels[v] = static_cast<int32_t>(L + 1);
+              // the filter holds every node reached before this level
+              if (levels[v] != static_cast<int32_t>(kBfsInf) && levels[v] != static_cast<int32_t>(L + 1))
+                error |= 0x400u;  // would overwrite an earlier level
+              levels[v] = static_cast<int32_t>(L + 1);
             }
           } else if (!kSssp) {
             for (uint32_t q = 0; q < kItems * 64; ++q) {
