@@ -157,6 +157,57 @@ def test_small_frontier_switching():
     _check(h, _dev(h), [0, 2500], "balanced")
 
 
+def _chain_of_blocks(path_len, n_mid, k_mid, blocks, salt):
+    """path, block, path, block, ..., path (all arcs both ways): big levels
+    inside each block, tiny ones along each path."""
+    P = path_len
+    parts_s, parts_d, parts_w = [], [], []
+    base = 0
+    for b in range(blocks + 1):
+        # path of P nodes starting at base, joined to the previous block's last node
+        parts_s.append(base + np.arange(P - 1)); parts_d.append(base + np.arange(1, P))
+        parts_w.append(np.full(P - 1, 3 + b))
+        if b:
+            parts_s.append(np.array([base - 1])); parts_d.append(np.array([base])); parts_w.append(np.array([2]))
+        base += P
+        if b == blocks:
+            break
+        blk = graphgen.uniform(n=n_mid, k=k_mid, wlo=1, whi=9, salt=salt + b)
+        parts_s.append(np.array([base - 1])); parts_d.append(np.array([base])); parts_w.append(np.array([2]))
+        parts_s.append(base + np.repeat(np.arange(n_mid), blk.degrees))
+        parts_d.append(base + blk.cols.astype(np.int64)); parts_w.append(blk.weights.astype(np.int64))
+        base += n_mid
+    s_all, d_all, w_all = (np.concatenate(x) for x in (parts_s, parts_d, parts_w))
+    return graphgen.from_edges(base, np.concatenate([s_all, d_all]), np.concatenate([d_all, s_all]),
+                               np.concatenate([w_all, w_all]), "blocks")
+
+
+def test_tile_counters_across_small_frontier_phases():
+    """Levels big enough for the dynamic part of the tile deal (more tiles
+    than wavefronts) inside the second of two blocks, reached after a
+    small-frontier phase that itself followed big levels: the per-XCD tile
+    counters those levels use must have been cleared by the small-frontier
+    kernel.  BFS (with scan levels) and SSSP equal the oracle."""
+    g = _chain_of_blocks(300, 200_000, 16, 2, salt=41)
+    dg = _dev(g)
+    exp_l = O.bfs(g.offsets, g.cols, 0)
+    exp_d = O.dijkstra(g.offsets, g.cols, g.weights, 0)
+    # the big levels of the second block deal tiles dynamically
+    deg = g.degrees
+    second = np.arange(g.n) >= 300 + 200_000 + 300
+    lv2 = exp_l[second & (exp_l != pins.BFS_INF)]
+    arcs = np.bincount(lv2, weights=deg[second & (exp_l != pins.BFS_INF)])
+    waves = lbg.grid_blocks() * 4
+    assert arcs.max() > waves * 1024  # the BFS tile: 64 lanes x 16 arcs
+    lbg.profile_enable(True, reset=True)
+    lv = _gpu_bfs(dg, 0, "balanced")
+    d = _gpu_sssp(dg, 0, "balanced")
+    lbg.profile_enable(False, reset=False)
+    assert np.array_equal(lv, exp_l)
+    assert np.array_equal(d, exp_d)
+    assert lbg.profile_read("bfs_small")["launches"] >= 2 and lbg.profile_read("sssp_small")["launches"] >= 2
+
+
 def test_degree_mdt_matches_oracle():
     """The device MDT (Section III-B histogram rule) equals the oracle's on
     skewed, uniform and grid graphs (an integer: compared exactly)."""
