@@ -445,8 +445,12 @@ int lbg_autotune_bins(const int32_t* offsets, const int32_t* cols, const uint32_
 const char* lbg_last_error(void);
 
 /* Per-kernel timing of the frontier-expansion kernels, for roofline
- * reporting.  While enabled, every expansion launch is bracketed by HIP events
- * on the caller's stream and its duration is accumulated process-wide,
+ * reporting.  While enabled, HIP events on the caller's stream time every
+ * expansion launch of single solves (one event when a batch of launches
+ * starts, then one after each launch, so a launch's duration runs from the
+ * event before it to the event after it; the events skip the system-scope
+ * cache fence, which the read-out does not need) and its duration is
+ * accumulated process-wide,
  * together with the work it did, separately for BFS and SSSP solves (they run
  * different kernels).  enable = 0 stops collection; reset = 1 clears the
  * totals. */

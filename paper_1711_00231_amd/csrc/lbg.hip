@@ -281,7 +281,12 @@ struct ScanHint {
 thread_local ScanHint g_scan_hint[4];
 thread_local uint32_t g_scan_hint_next = 0;
 thread_local std::vector<hipEvent_t> g_events;
-thread_local std::vector<int64_t> g_event_level;  // per event pair: level, or -1 = small-frontier launch
+// Profiling mode: per timed launch, its level (-1 = small-frontier launch)
+// and the index of the event recorded right after it; the launch's interval
+// starts at the event before that one (one event per batch start, then one
+// after each launch).
+thread_local std::vector<int64_t> g_event_level;
+thread_local std::vector<size_t> g_event_end;
 
 Ctl* pinned_ctl() {
   if (!g_pinned.p) {
@@ -292,10 +297,14 @@ Ctl* pinned_ctl() {
   return g_pinned.p;
 }
 
+// Timing events of profiling mode.  They are read only after the solve has
+// synchronised its stream, so they need no system-scope fence when
+// recorded; without one a record does not write back and invalidate the
+// caches between two levels, which would slow the level after it.
 hipEvent_t event_at(size_t i) {
   while (g_events.size() <= i) {
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     g_events.push_back(e);
   }
   return g_events[i];
@@ -615,6 +624,7 @@ int solve(const Problem& P) {
   bool small = false, used_small = false;
   size_t nev = 0;
   g_event_level.clear();
+  g_event_end.clear();
   const uint64_t level_cap = static_cast<uint64_t>(P.n) + 2;
   auto mark = [&]() -> int {
     hipEvent_t e = event_at(nev++);
@@ -623,8 +633,8 @@ int solve(const Problem& P) {
     return LBG_OK;
   };
   for (;;) {
+    if (profiling && (rc = mark()) != LBG_OK) return rc;  // the batch's first interval starts here
     if (small) {
-      if (profiling && (rc = mark()) != LBG_OK) return rc;
       const uint32_t max_levels = static_cast<uint32_t>(level_cap + 1 - L);
       if (P.is_sssp && packed) {
         if (narrow) hipLaunchKernelGGL((lbg::k_expand_small<true, true, true>), dim3(1), dim3(lbg::kSmallBlock), 0, st, a, L, max_levels);
@@ -640,15 +650,16 @@ int solve(const Problem& P) {
       if (profiling) {
         if ((rc = mark()) != LBG_OK) return rc;
         g_event_level.push_back(-1);
+        g_event_end.push_back(nev - 1);
       }
     } else {
       for (uint32_t k = 0; k < batch; ++k, ++L) {
-        if (profiling && (rc = mark()) != LBG_OK) return rc;
         launch(L);
         HIP_TRY(hipGetLastError());
-        if (profiling) {
+        if (profiling) {  // ends this launch's interval and starts the next one's
           if ((rc = mark()) != LBG_OK) return rc;
           g_event_level.push_back(L);
+          g_event_end.push_back(nev - 1);
         }
       }
       batch = std::min<uint32_t>(batch * 2, 64);
@@ -698,10 +709,10 @@ int solve(const Problem& P) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     lbg_profile& gp = g_prof[P.is_sssp ? 1 : 0];
     lbg_profile& pp = g_prof[P.is_sssp ? 4 : 3];
-    for (size_t k = 0; k + 1 < nev; k += 2) {
+    for (size_t j = 0; j < g_event_end.size(); ++j) {
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, g_events[k], g_events[k + 1]));
-      const int64_t lv = g_event_level[k / 2];
+      HIP_TRY(hipEventElapsedTime(&ms, g_events[g_event_end[j] - 1], g_events[g_event_end[j]]));
+      const int64_t lv = g_event_level[j];
       if (lv < 0) {
         pp.launches += 1;
         pp.kernel_ms += ms;
