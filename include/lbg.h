@@ -167,6 +167,17 @@ int lbg_bfs(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, i
 int lbg_set_bfs_scan_min(int64_t arcs);
 int64_t lbg_get_bfs_scan_min(void);
 
+/* Element addressing of the kernels of single, batched and engine solves
+ * that start later.  mode 0 (the default): 32-bit element offsets from a
+ * scalar base whenever every array the solve touches stays below 4 GiB
+ * (n < 2^29 nodes, m < 2^30 arcs), 64-bit addresses otherwise; mode 1:
+ * 64-bit addresses always (the form graphs above those bounds take; results
+ * are the same, this exists so that form can be checked on small graphs).
+ * Process-wide.  LBG_EINVAL for any other mode.  lbg_get_addressing returns
+ * the setting. */
+int lbg_set_addressing(int32_t mode);
+int32_t lbg_get_addressing(void);
+
 /* SSSP distances from src.  dist_out[v] = minimum total weight of a directed
  * path from src to v, UINT32_MAX if unreachable.  Precondition: every finite
  * shortest-path weight is below UINT32_MAX (e.g. (n-1) * max weight <

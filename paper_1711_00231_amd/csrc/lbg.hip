@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <chrono>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -235,6 +236,7 @@ std::mutex g_bins_mu;
 lbg_bins g_bins{256, 16, 1024};  // what the autotuner picks on R-MAT scale 22
 int32_t g_slice_min = 512;       // LBG_SLICED: degree from which a node is split by slice
 int64_t g_bfs_scan_min = -1;     // balanced BFS: arcs from which a level runs in scan mode (< 0: n / 4)
+std::atomic<int32_t> g_addressing{0};  // 0: 32-bit element offsets when every array fits, 1: always 64-bit
 int32_t g_hier_mdt = 0;          // LBG_HIER: fixed MDT (0 = the histogram rule per solve)
 
 // Sub-iteration schedule of this thread's last LBG_HIER solve (read back
@@ -503,7 +505,8 @@ int solve(const Problem& P) {
   const int sv = P.is_sssp ? 1 : 0;
   // 32-bit element offsets are enough when every array stays below 4 GiB
   // (the slice offsets have 8n + 1 entries, the split offsets n + children + 1)
-  const bool narrow = (split ? P.n + P.children : P.n) < (sl ? (1 << 26) : (1 << 29)) &&
+  const bool narrow = g_addressing.load() == 0 &&
+                      (split ? P.n + P.children : P.n) < (sl ? (1 << 26) : (1 << 29)) &&
                       P.m < (int64_t{1} << 30);
   const int nw = narrow ? 1 : 0;
   const int init_blocks = static_cast<int>(
@@ -943,7 +946,8 @@ int batch_solve(const int32_t* offsets, const int32_t* cols, const uint32_t* wei
 
   HIP_TRY(hipMemcpyAsync(ws + Lay.qtab, qt.data(), sizeof(lbg::QInfo) * qt.size(),
                          hipMemcpyHostToDevice, st));
-  const bool narrow = n < (1 << 29) && m < (int64_t{1} << 30) && rows < (int64_t{1} << 29);
+  const bool narrow = g_addressing.load() == 0 && n < (1 << 29) && m < (int64_t{1} << 30) &&
+                      rows < (int64_t{1} << 29);
   const Grids& GR = grids();
   int64_t max_len = 1;
   for (const lbg::QInfo& I : qt) max_len = std::max<int64_t>(max_len, I.row_len);
@@ -1119,7 +1123,8 @@ int lbg_engine_create(const int32_t* offsets, const int32_t* cols, const uint32_
   e->max_rows = max_rows;
   e->lay = engine_layout(max_queries, max_rows, max_level_arcs);
   e->ws = static_cast<char*>(workspace);
-  e->narrow = n < (1 << 29) && m < (int64_t{1} << 30) && max_rows < (int64_t{1} << 29);
+  e->narrow = g_addressing.load() == 0 && n < (1 << 29) && m < (int64_t{1} << 30) &&
+              max_rows < (int64_t{1} << 29);
   e->qt.assign(static_cast<size_t>(max_queries), lbg::QInfo{});
   e->state.assign(static_cast<size_t>(max_queries), 0);
   void* p1 = nullptr;
@@ -1517,6 +1522,14 @@ int32_t lbg_get_slice_min(void) {
   std::lock_guard<std::mutex> lk(g_bins_mu);
   return g_slice_min;
 }
+
+int lbg_set_addressing(int32_t mode) {
+  if (mode != 0 && mode != 1) return fail(LBG_EINVAL, "addressing mode must be 0 or 1 (got %d)", mode);
+  g_addressing.store(mode);
+  return LBG_OK;
+}
+
+int32_t lbg_get_addressing(void) { return g_addressing.load(); }
 
 int lbg_set_bfs_scan_min(int64_t arcs) {
   std::lock_guard<std::mutex> lk(g_bins_mu);

@@ -98,6 +98,10 @@ def _load():
     lib.lbg_slice_nodes.argtypes = [i32]
     lib.lbg_set_slice_min.restype = ctypes.c_int
     lib.lbg_set_slice_min.argtypes = [i32]
+    lib.lbg_set_addressing.restype = ctypes.c_int
+    lib.lbg_set_addressing.argtypes = [i32]
+    lib.lbg_get_addressing.restype = i32
+    lib.lbg_get_addressing.argtypes = []
     lib.lbg_set_bfs_scan_min.restype = ctypes.c_int
     lib.lbg_set_bfs_scan_min.argtypes = [i64]
     lib.lbg_get_bfs_scan_min.restype = i64
@@ -333,6 +337,16 @@ def set_bfs_scan_min(arcs: int) -> None:
 
 def get_bfs_scan_min() -> int:
     return int(lib.lbg_get_bfs_scan_min())
+
+
+def set_addressing(mode: int) -> None:
+    """0: 32-bit element offsets whenever the arrays fit (default), 1: 64-bit
+    addresses always (see lbg_set_addressing)."""
+    _check(lib.lbg_set_addressing(int(mode)))
+
+
+def get_addressing() -> int:
+    return int(lib.lbg_get_addressing())
 
 
 def slice_graph(g: DeviceGraph, stream=None) -> SlicedGraph:

@@ -209,6 +209,18 @@ def test_slice_min_setting():
     lbgmod.set_slice_min(saved)
 
 
+def test_addressing_setting():
+    assert lbgmod.get_addressing() == 0
+    for bad in (-1, 2, 64):
+        with pytest.raises(lbgmod.LbgError):
+            lbgmod.set_addressing(bad)
+        assert lbgmod.get_addressing() == 0
+    lbgmod.set_addressing(1)
+    assert lbgmod.get_addressing() == 1
+    lbgmod.set_addressing(0)
+    assert lbgmod.get_addressing() == 0
+
+
 def test_slice_sizes():
     for n, S in ((1, 64), (8, 64), (512, 64), (513, 128), (4194304, 524288), (1000, 128)):
         assert lbgmod.slice_nodes(n) == S
