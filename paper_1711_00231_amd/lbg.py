@@ -553,16 +553,51 @@ def sssp_noalloc(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tenso
     return (out, st.as_dict()) if stats else out
 
 
+_QUERY_DTYPE = None
+
+
+def _query_dtype():
+    global _QUERY_DTYPE
+    if _QUERY_DTYPE is None:
+        import numpy as np
+
+        _QUERY_DTYPE = np.dtype({"names": [f for f, _ in Query._fields_],
+                                 "formats": ["<i4", "<i4", "<i4", "<i4", "<i8"],
+                                 "offsets": [getattr(Query, f).offset for f, _ in Query._fields_],
+                                 "itemsize": ctypes.sizeof(Query)})
+    return _QUERY_DTYPE
+
+
 def batch_queries(queries):
     """Query array from (src, lo, hi, kind[, out_off]) tuples; missing row
-    offsets are assigned back to back.  Returns (Query array, total_rows)."""
-    arr = (Query * len(queries))()
-    off = 0
-    for i, q in enumerate(queries):
-        src, lo, hi, kind = (int(x) for x in q[:4])
-        o = int(q[4]) if len(q) > 4 else off
-        arr[i].src, arr[i].lo, arr[i].hi, arr[i].kind, arr[i].out_off = src, lo, hi, kind, o
-        off = max(off, o + hi - lo)
+    offsets are assigned back to back.  Returns (Query array, total_rows).
+    The array is a ctypes view of a numpy record array (attribute ``rec``)."""
+    import numpy as np
+
+    k = len(queries)
+    rec = np.zeros(k, dtype=_query_dtype())
+    widths = {len(q) for q in queries}
+    if k and widths <= {4, 5} and len(widths) == 1:
+        a = np.array(queries, dtype=np.int64).reshape(k, -1)
+        for j, f in enumerate(("src", "lo", "hi", "kind")):
+            rec[f] = a[:, j]
+        size = a[:, 2] - a[:, 1]
+        if a.shape[1] == 5:
+            rec["out_off"] = a[:, 4]
+            off = int(max(0, (a[:, 4] + size).max()))
+        else:
+            ends = np.cumsum(size)
+            rec["out_off"] = ends - size
+            off = int(max(0, ends[-1]))
+    else:  # mixed tuple lengths: offsets follow the sequence
+        off = 0
+        for i, q in enumerate(queries):
+            src, lo, hi, kind = (int(x) for x in q[:4])
+            o = int(q[4]) if len(q) > 4 else off
+            rec[i] = (src, lo, hi, kind, o)
+            off = max(off, o + hi - lo)
+    arr = (Query * k).from_buffer(rec)
+    arr.rec = rec
     return arr, off
 
 
@@ -586,7 +621,7 @@ def batch_solve(g: DeviceGraph, queries, out: torch.Tensor | None = None, total_
         if g.host_offsets is None:
             raise ValueError("total_arcs is required when the graph has no host offsets")
         ho = g.host_offsets
-        total_arcs = int(sum(int(ho[q.hi]) - int(ho[q.lo]) for q in qarr))
+        total_arcs = int((ho[qarr.rec["hi"]] - ho[qarr.rec["lo"]]).sum()) if len(qarr) else 0
     if out is None:
         out = torch.empty(max(rows, 1), dtype=torch.int32, device=g.offsets.device)
     need = batch_workspace_bytes(len(qarr), out.numel(), total_arcs)
