@@ -167,8 +167,9 @@ int lbg_bfs(const int32_t* offsets, const int32_t* cols, int32_t n, int64_t m, i
 int lbg_set_bfs_scan_min(int64_t arcs);
 int64_t lbg_get_bfs_scan_min(void);
 
-/* Element addressing of the kernels of single, batched and engine solves
- * that start later.  mode 0 (the default): 32-bit element offsets from a
+/* Element addressing of the kernels of single and batched solves that start
+ * later and of engines created later (an engine keeps the form it was
+ * created with).  mode 0 (the default): 32-bit element offsets from a
  * scalar base whenever every array the solve touches stays below 4 GiB
  * (n < 2^29 nodes, m < 2^30 arcs), 64-bit addresses otherwise; mode 1:
  * 64-bit addresses always (the form graphs above those bounds take; results
