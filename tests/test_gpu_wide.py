@@ -135,3 +135,27 @@ def test_engine_wide():
         step += 1
         assert step < 10000
     assert done == total
+
+
+def test_noalloc_sssp_wide():
+    for g, srcs in _cases()[:4]:
+        dg = _dev(g)
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for s in srcs:
+            lbg.sssp_noalloc(dg, s, out=out)
+            assert np.array_equal(out.cpu().numpy().view(np.uint32),
+                                  O.dijkstra(g.offsets, g.cols, g.weights, s)), (g.name, s)
+
+
+def test_forms_alternate_on_one_workspace():
+    """Narrow and wide solves of one graph in turn, on one workspace (the
+    per-graph record of scan levels is shared by both forms)."""
+    g = graphgen.rmat(16)
+    dg = _dev(g)
+    ws = lbg.Workspace()
+    srcs = [int(s) for s in graphgen.sources(g, 4, graphgen.FAMILY_RMAT)]
+    for k, s in enumerate(srcs * 2):
+        lbg.set_addressing(k % 2)
+        assert np.array_equal(lbg.bfs(dg, s, workspace=ws).cpu().numpy(), O.bfs(g.offsets, g.cols, s)), (k, s)
+        assert np.array_equal(lbg.sssp(dg, s, workspace=ws, ordered=True).cpu().numpy().view(np.uint32),
+                              O.dijkstra(g.offsets, g.cols, g.weights, s)), (k, s)
