@@ -133,6 +133,14 @@ def algorithmic_bytes(kind, prof):
     return 12 * loaded + 4 * prof["updates"] + 20 * prof["frontier_entries"]
 
 
+def hmean_gteps(times_ms, arcs):
+    """Harmonic mean over solves of arcs / time (the Graph500 convention for
+    a set of sources), in GTEPS: len / sum(time_i / arcs_i)."""
+    if not len(times_ms):
+        return None
+    return len(times_ms) / sum((t / 1e3) / max(int(a), 1) for t, a in zip(times_ms, arcs)) / 1e9
+
+
 def host_info():
     """Cores this process may run on and the CPU model, read on the machine
     that runs the benchmark."""
@@ -249,6 +257,7 @@ def run_plain(args, lbg, torch, dev):
             if lat is not None:
                 lat["bfs"].append((t1 - t) * 1e3)
                 lat["sssp"].append((t2 - t1) * 1e3)
+                lat["arcs"].append(reach_arcs[s])
             arcs += 2 * reach_arcs[s]
         return arcs
 
@@ -259,7 +268,7 @@ def run_plain(args, lbg, torch, dev):
     # Timed region.  With profiling on, the library brackets every expansion
     # launch with HIP events on the solve's stream (BFS and SSSP kernels are
     # accumulated separately).
-    lat = {"bfs": [], "sssp": []}
+    lat = {"bfs": [], "sssp": [], "arcs": []}
     if not args.no_profile:
         lbg.profile_enable(True, reset=True)
     torch.cuda.synchronize()
@@ -304,6 +313,10 @@ def run_plain(args, lbg, torch, dev):
         "bfs_ms_p99": round(float(np.percentile(lat["bfs"], 99)), 4),
         "sssp_ms_p50": round(float(np.percentile(lat["sssp"], 50)), 4),
         "sssp_ms_p99": round(float(np.percentile(lat["sssp"], 99)), 4),
+        # per-solve harmonic means over the timed sources (host clock around
+        # each solve, which waits for its result)
+        "bfs_gteps_hmean": round(hmean_gteps(lat["bfs"], lat["arcs"]), 4),
+        "sssp_gteps_hmean": round(hmean_gteps(lat["sssp"], lat["arcs"]), 4),
     }
     if order_ms is not None:
         out["order_build_ms"] = round(order_ms, 3)

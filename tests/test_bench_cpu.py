@@ -85,3 +85,11 @@ def test_workload_table():
     assert g.n == 1 << 14 and len(srcs) == 1 and not sym and "uniform" in desc
     with pytest.raises(SystemExit):
         bench.make_workload("nope")
+
+
+def test_harmonic_mean_gteps():
+    # two solves of 1e9 arcs in 1 s and 2 s: 2 / (1 + 2) GTEPS
+    assert abs(bench.hmean_gteps([1000.0, 2000.0], [10**9, 10**9]) - 2 / 3) < 1e-12
+    # equal rates give that rate whatever the sizes
+    assert abs(bench.hmean_gteps([1.0, 4.0], [10**6, 4 * 10**6]) - 1.0) < 1e-12
+    assert bench.hmean_gteps([], []) is None
