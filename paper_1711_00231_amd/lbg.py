@@ -205,6 +205,18 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _out(out, n: int, device, what: str = "out"):
+    """The caller's result tensor, checked (the library writes n 4-byte
+    words through its pointer and cannot see its size), or a new one."""
+    if out is None:
+        return torch.empty(n, dtype=torch.int32, device=device)
+    if (out.dtype not in (torch.int32, torch.uint32) or out.dim() != 1 or not out.is_contiguous()
+            or out.device != device or out.numel() < n):
+        raise ValueError(f"{what} must be a contiguous 1-D int32 tensor of at least {n} elements on "
+                         f"{device} (got shape {tuple(out.shape)}, {out.dtype}, on {out.device})")
+    return out
+
+
 def workspace_bytes(n: int, m: int, strategy="balanced", sssp: bool = False) -> int:
     return int(lib.lbg_workspace_bytes(n, m, _strategy(strategy), int(sssp)))
 
@@ -224,6 +236,19 @@ class DeviceGraph:
     packed: "tuple | None" = None  # (arcs tensor, wbits) from lbg_pack_arcs
     split: "SplitGraph | None" = None
     ordered: "OrderedGraph | None" = None
+
+    def __post_init__(self):
+        dev = self.offsets.device
+        for name, t, types in (("offsets", self.offsets, (torch.int32,)), ("cols", self.cols, (torch.int32,)),
+                               ("weights", self.weights, (torch.int32, torch.uint32))):
+            if t is not None and (t.dtype not in types or t.dim() != 1 or not t.is_contiguous()
+                                  or t.device != dev):
+                raise ValueError(f"{name} must be a contiguous 1-D 32-bit integer tensor on {dev} "
+                                 f"(got shape {tuple(t.shape)}, {t.dtype}, on {t.device})")
+        if self.offsets.numel() < 1:
+            raise ValueError("offsets needs n + 1 >= 1 entries")
+        if self.weights is not None and self.weights.numel() != self.cols.numel():
+            raise ValueError(f"weights has {self.weights.numel()} entries for {self.cols.numel()} arcs")
 
     @property
     def n(self) -> int:
@@ -458,8 +483,7 @@ def bfs(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None 
     tensor, or (tensor, stats dict) if ``stats``.  ``mdt``: split size of
     the 'split' strategy (None: the histogram rule)."""
     s = _strategy(strategy)
-    if out is None:
-        out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    out = _out(out, g.n, g.offsets.device)
     need = workspace_bytes(g.n, g.m, s, False) if s != SPLIT else 0  # sized below
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
@@ -498,8 +522,7 @@ def sssp(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tensor | None
         raise ValueError("packed arcs and the ordered copy are separate layouts")
     if g.weights is None:
         raise ValueError("sssp needs weights")
-    if out is None:
-        out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    out = _out(out, g.n, g.offsets.device)
     need = workspace_bytes(g.n, g.m, s, True) if s != SPLIT else 0  # sized below
     ws = _ws(workspace, need, g.offsets.device)
     coo = g.ensure_coo() if s in (EDGE, EDGE_NOCHUNK) else None
@@ -544,8 +567,7 @@ def sssp_noalloc(g: DeviceGraph, src: int, strategy="balanced", out: torch.Tenso
     that cannot allocate; calls that overlap on one GPU race."""
     if g.weights is None:
         raise ValueError("sssp needs weights")
-    if out is None:
-        out = torch.empty(g.n, dtype=torch.int32, device=g.offsets.device)
+    out = _out(out, g.n, g.offsets.device)
     st = Stats()
     rc = lib.lbg_sssp_noalloc(_ptr(g.offsets), _ptr(g.cols), _ptr(g.weights), g.n, g.m, int(src), _ptr(out),
                               _strategy(strategy), ctypes.byref(st) if stats else None, _stream(stream))
@@ -622,8 +644,7 @@ def batch_solve(g: DeviceGraph, queries, out: torch.Tensor | None = None, total_
             raise ValueError("total_arcs is required when the graph has no host offsets")
         ho = g.host_offsets
         total_arcs = int((ho[qarr.rec["hi"]] - ho[qarr.rec["lo"]]).sum()) if len(qarr) else 0
-    if out is None:
-        out = torch.empty(max(rows, 1), dtype=torch.int32, device=g.offsets.device)
+    out = _out(out, max(rows, 1), g.offsets.device)
     need = batch_workspace_bytes(len(qarr), out.numel(), total_arcs)
     if need == 0:
         raise LbgError(EINVAL, "invalid batch sizes")
