@@ -569,6 +569,15 @@ typedef struct lbg_engine lbg_engine;
  * of the arc counts of the instances that may be queried concurrently. */
 size_t lbg_engine_workspace_bytes(int32_t max_queries, int64_t max_rows, int64_t max_level_arcs);
 
+/* Create an engine over the packed graph (device offsets/cols/weights as for
+ * lbg_batch_solve) with the given capacities, result rows `rows_out` and a
+ * workspace of at least lbg_engine_workspace_bytes (256-byte aligned); all
+ * stay the caller's and must outlive the engine.  *engine receives a host
+ * handle (the library's pinned host buffers for the slot table and
+ * read-backs) that lbg_engine_destroy frees.  LBG_EINVAL for a null
+ * pointer, n <= 0 or a misaligned workspace, LBG_ERANGE for m outside
+ * [0, INT32_MAX] or invalid capacities, LBG_ENOMEM for a small workspace,
+ * LBG_EHIP if the pinned host buffers cannot be allocated. */
 int lbg_engine_create(const int32_t* offsets, const int32_t* cols, const uint32_t* weights,
                       int32_t n, int64_t m, int32_t max_queries, int64_t max_rows,
                       int64_t max_level_arcs, uint32_t* rows_out, void* workspace,
@@ -594,6 +603,8 @@ int lbg_engine_release(lbg_engine* e, int32_t slot);
 /* Cumulative stats, number of queued + running queries, next level index. */
 int lbg_engine_info(const lbg_engine* e, lbg_stats* stats, int32_t* running, uint32_t* level);
 
+/* Wait for the engine's stream and free the handle and its pinned host
+ * buffers (not the caller's graph, rows or workspace).  NULL is a no-op. */
 void lbg_engine_destroy(lbg_engine* e);
 
 /* Tile of edges one workgroup of the balanced expansion processes (the
